@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the PaLD hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one full evaluation (pass 1: focus sizes, pass 2: cohesion) of the
+n = 16384 integer-grid workload (points uniform in {0..31}^3, squared
+Euclidean distances as float32: heavy ties), with D already resident in HBM.
+
+Prints ONE JSON line on stdout.  `value` is triplet comparisons per second in
+G/s: 2 n^3 comparison terms per evaluation (one per ordered pair and third
+point in each of the two defining sums) divided by the time per step.
+
+`roofline` describes the dominant kernel (pass 2, cohesion), whose launches
+are timed with HIP events on the stream they run on.  Its algorithmic work is
+6 VALU lane-operations per (x, y, z) term with y != x (one min, two compares,
+two selects, one add) = 6 n^2 (n-1) per launch, set against the VALU issue
+peak of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s.
+
+`cpu_baseline` is the FP64 oracle on the host cores for a bounded sample of
+rows of the same matrix (2 n^2 comparison terms per row).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 16384
+SEED = 3
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3216 T lane-ops/s
+PASS2_OPS_PER_TERM = 6
+PASS1_OPS_PER_TERM = 3
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(D: np.ndarray, target_s: float = 12.0):
+    """Oracle throughput on the host cores for a bounded row sample of D."""
+    import oracle
+
+    n = D.shape[0]
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(123)
+    probe_rows = max(threads, 4)
+    rows = rng.choice(n, size=probe_rows, replace=False)
+    t0 = time.perf_counter()
+    oracle.pald_rows(D, rows, threads=threads)
+    t_probe = time.perf_counter() - t0
+    per_row = t_probe / probe_rows
+    k = int(max(probe_rows, min(n, (target_s / max(per_row, 1e-9)))))
+    k = max(threads, (k // threads) * threads)
+    rows = rng.choice(n, size=k, replace=False)
+    t0 = time.perf_counter()
+    oracle.pald_rows(D, rows, threads=threads)
+    t = time.perf_counter() - t0
+    value = k * 2.0 * n * n / t / 1e9
+    return {
+        "value": round(value, 4),
+        "unit": "G triplet comparisons/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{k} random rows of U and C of the n={n} grid3d matrix (2*n^2 terms per row), "
+                  f"{t:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=N, help="matrix size (default 16384)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(rerun with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2307_16652_amd import pald, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if not os.path.exists(pald.LIB_PATH):
+        from paper_2307_16652_amd import build as pald_build
+
+        pald_build.build()
+    pald.load_library()
+
+    n = args.n
+    dev = torch.device("cuda:0")
+    progress(f"generating grid3d n={n} seed={SEED}")
+    D = synth.grid3d(n=n, seed=SEED)
+    Dg = torch.from_numpy(D).to(dev)
+    ws = pald.workspace(n, dev)
+    U = torch.empty((n, n), dtype=torch.int32, device=dev)
+    C = torch.empty((n, n), dtype=torch.float32, device=dev)
+
+    def step(timing: bool):
+        pald.cohesion(Dg, ws=ws, out_u=U, out_c=C, timing=timing)
+
+    progress(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    pald.timings_collect()  # discard
+
+    progress(f"timing x{args.steps}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = pald.timings_collect()
+    ms_per_step = elapsed / args.steps * 1e3
+    terms = 2.0 * n**3
+    value = terms / (ms_per_step / 1e3) / 1e9
+    progress(f"{ms_per_step:.1f} ms/step, {value:.1f} G/s; kernels {kt}")
+
+    p2_ms = kt["pass2_cohesion"][0] / kt["pass2_cohesion"][1]
+    p1_ms = kt["pass1_focus"][0] / kt["pass1_focus"][1]
+    p2_ops = PASS2_OPS_PER_TERM * n * n * (n - 1)
+    p2_achieved = p2_ops / (p2_ms / 1e3) / 1e12
+    p1_ops = PASS1_OPS_PER_TERM * (n * (n + 1) / 2) * n
+    roofline = {
+        "bound": "alu",
+        "achieved": round(p2_achieved, 3),
+        "peak": round(VALU_PEAK_TOPS, 3),
+        "unit": "T VALU lane-ops/s",
+        "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
+        "traffic": None,
+        "kernel": "pass2_cohesion",
+        "kernel_ms": round(p2_ms, 3),
+    }
+    kernels = {k: round(v[0] / v[1], 3) for k, v in kt.items()}
+
+    extra = {}
+    if not args.no_comparators:
+        progress("comparator: float64-accumulate pass 2")
+        Cf = torch.empty_like(C)
+        pald.cohesion(Dg, ws=ws, out_u=U, out_c=Cf, accum="f64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pald.cohesion(Dg, ws=ws, out_u=U, out_c=Cf, accum="f64", timing=True)
+        torch.cuda.synchronize()
+        t_f64 = time.perf_counter() - t0
+        kf = pald.timings_collect()
+        diff = (C.double() - Cf.double()).abs() / Cf.double().abs().clamp_min(1e-300)
+        diff = torch.where(Cf == 0, (C != 0).double(), diff)
+        extra["comparators"] = {
+            "f64_accumulate_ms_per_step": round(t_f64 * 1e3, 2),
+            "f64_accumulate_pass2_ms": round(kf["pass2_cohesion"][0], 3),
+            "compensated_vs_f64_max_rel": float(diff.max().item()),
+        }
+        del Cf
+    extra["pass1_focus_lane_ops_frac"] = round(p1_ops / (p1_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
+
+    base = None
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle rows)")
+        base = cpu_baseline(D)
+
+    out = {
+        "metric": "triplet comparisons/sec (G/s) + % VALU peak, n=16384 fp32",
+        "value": round(value, 2),
+        "unit": "G triplet comparisons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grid3d", "n": n, "seed": SEED,
+                   "points": "uniform in {0..31}^3", "distance": "squared euclidean (integer, fp32)",
+                   "accumulation": "fp32 runs + Kahan partials, fp64 final reduce"},
+        "roofline": roofline,
+        "cpu_baseline": base,
+        "kernels_ms": kernels,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * pald.h -- C ABI of libpald, partitioned local depths (PaLD) on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * PaLD (Devarakonda & Ballard, arXiv 2307.16652; the method itself is from
+ * Berenhaut et al.) turns an n x n matrix of pairwise distances D into
+ *
+ *   U  -- local focus sizes (Section 2):
+ *           U_xy = #{ z : d_zx <= d_xy  or  d_zy <= d_xy },  int32, symmetric.
+ *         The diagonal follows the same formula at y = x, i.e.
+ *         U_xx = #{ z : d_zx <= 0 } (1 unless distinct points coincide).
+ *   C  -- cohesion (Section 2, Eq. (cohesion); Section 3, Eq. (fxz)):
+ *           C_xz = 1/(n-1) * sum_{y != x} [z in U_xy] * s(d_zx, d_zy) / U_xy
+ *         with the tie rule s(p, q) = [p < q] + 1/2 [p == q] (Section 5:
+ *         support is split on ties), float32, not symmetric.  Row sums of C
+ *         are the local depths; the sum of all entries is n/2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are row-major with a leading dimension (elements between the
+ *   starts of consecutive rows) >= n.  D, U, C and workspace pointers are
+ *   DEVICE pointers owned by the caller; the library never frees them.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued asynchronously on it and PALD_OK means "enqueued";
+ *   results are valid once the stream has been synchronised.
+ * - Input contract: every d_ij finite and >= 0, D exactly symmetric, zero
+ *   diagonal.  The hot calls do not check the data (use pald_check_input);
+ *   on invalid data they produce unspecified values but never access memory
+ *   outside the described buffers.  -0.0 is treated as +0.0.
+ * - Argument errors (null pointers, n < 2, leading dimension < n, workspace
+ *   too small, an unknown option) are reported synchronously with
+ *   PALD_ERR_ARG / PALD_ERR_UNSUPPORTED and nothing is enqueued.  A failed
+ *   launch reports PALD_ERR_DEVICE.
+ * - The hot calls allocate no device memory.  Batch plans own a small device
+ *   descriptor allocated at plan creation.
+ * - Comparisons are made on the float32 input values exactly as given, so U
+ *   is exact.  C accumulates float32 weights 1/U in float32 runs of 8 terms
+ *   folded into per-tile Kahan-compensated partials; float64 is used only for
+ *   the final cross-tile reduction and the 1/(n-1) scaling.  Relative error
+ *   of every C entry <= 11 * 2^-24 (6.6e-7); entries whose exact value is 0
+ *   are exactly 0.  Results are deterministic for a fixed configuration.
+ */
+#ifndef PALD_H
+#define PALD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pald_status {
+    PALD_OK = 0,
+    PALD_ERR_ARG = 1,         /* bad argument, nothing enqueued */
+    PALD_ERR_INPUT = 2,       /* pald_check_input found invalid data */
+    PALD_ERR_DEVICE = 3,      /* HIP runtime or launch error */
+    PALD_ERR_NOMEM = 4,       /* host allocation or plan descriptor allocation failed */
+    PALD_ERR_UNSUPPORTED = 5  /* option combination not implemented */
+} pald_status;
+
+/* Algorithm used for the two passes. */
+enum {
+    PALD_VARIANT_AUTO = 0,     /* library choice (currently pairwise) */
+    PALD_VARIANT_PAIRWISE = 1, /* Section 3 pairwise algorithm: output-stationary
+                                  (x,y) tiles for U, (x,z) tiles for C */
+    PALD_VARIANT_TRIPLET = 2   /* Section 3 triplet algorithm: one visit per
+                                  unordered triple, shared comparisons */
+};
+
+/* Accumulation of the cohesion sums. */
+enum {
+    PALD_ACC_COMPENSATED = 0, /* float32 runs + Kahan partials, float64 final reduce */
+    PALD_ACC_F64 = 1          /* plain float64 accumulator (reference form) */
+};
+
+/* Flags. */
+#define PALD_FLAG_TIMING 1u /* record device time of every kernel launched by this
+                               call; read with pald_timings_collect */
+
+typedef struct pald_options {
+    int32_t variant;     /* PALD_VARIANT_* */
+    int32_t accum;       /* PALD_ACC_* */
+    int32_t y_chunks;    /* pass-2 split of the y range over workgroups; 0 = automatic */
+    int32_t z_chunks;    /* pass-1 split of the z range over workgroups; 0 = automatic */
+    uint32_t flags;      /* PALD_FLAG_* */
+    int32_t reserved[3]; /* must be zero */
+} pald_options;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *pald_status_string(int32_t status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t pald_version(void);
+
+/* Bytes of device workspace pald_cohesion needs for an n x n problem with
+ * options `opt` (NULL = defaults).  Returns 0 if n < 2 or opt is invalid. */
+size_t pald_workspace_bytes(int64_t n, const pald_options *opt);
+
+/*
+ * Pass 1 only: the local focus sizes U (Section 2 definition, the first loop
+ * of the pairwise algorithm in Section 3).  Needs no workspace.
+ *   D    [n x ldd]  float32 distances, device, read only
+ *   U    [n x ldu]  int32 output, device; every entry of the n x n block written
+ * Errors: PALD_ERR_ARG for null D/U, n < 2, ldd < n, ldu < n;
+ * PALD_ERR_UNSUPPORTED for an unknown option or nonzero reserved field.
+ */
+pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd,
+                             int32_t *U, int64_t ldu,
+                             void *stream, const pald_options *opt);
+
+/*
+ * Both passes: U (optional) and the cohesion matrix C (Section 3, Eq. (fxz)
+ * with ties split as in Section 5 and y ranging over S \ {x}).
+ *   D    [n x ldd]  float32 distances, device, read only
+ *   U    [n x ldu]  int32 output, device, or NULL to skip writing U (ldu ignored)
+ *   C    [n x ldc]  float32 output, device; every entry of the n x n block written
+ *   ws   device workspace of at least pald_workspace_bytes(n, opt) bytes; its
+ *        contents on entry are ignored and on exit unspecified
+ * Errors: PALD_ERR_ARG for null D/C/ws, n < 2, a leading dimension < n, small
+ * ws; PALD_ERR_UNSUPPORTED for an unknown variant/accum or nonzero reserved.
+ */
+pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd,
+                          int32_t *U, int64_t ldu,
+                          float *C, int64_t ldc,
+                          void *ws, size_t ws_bytes,
+                          void *stream, const pald_options *opt);
+
+/*
+ * Validates D against the input contract.  Synchronous: enqueues a check on
+ * `stream`, waits for it and returns PALD_OK or PALD_ERR_INPUT.  If
+ * `flags_out` is not NULL it receives a bit set of the problems found:
+ * 1 = NaN, 2 = infinity, 4 = negative value, 8 = asymmetric pair,
+ * 16 = nonzero diagonal entry.  ws needs >= 256 bytes.
+ */
+pald_status pald_check_input(const float *D, int64_t n, int64_t ldd,
+                             void *ws, size_t ws_bytes, void *stream,
+                             uint32_t *flags_out);
+
+/*
+ * Batched mode: many independent matrices of different sizes in one
+ * persistent launch (no batching in the paper; it is a GPU-side extension).
+ *
+ * Packed layout: matrix i has n_i rows, leading dimension n_i, and starts at
+ * element offset off_i = sum_{j<i} n_j^2 of D_packed, U_packed and C_packed.
+ *
+ * pald_batch_plan_create copies n_host, chooses tile shapes and y-splits per
+ * matrix size, builds the work queue and uploads it to the current device
+ * (this is the only allocating call; it is synchronous).  Every n_i >= 2.
+ */
+typedef struct pald_batch_plan pald_batch_plan;
+
+pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host,
+                                   const pald_options *opt,
+                                   pald_batch_plan **plan_out);
+
+/* Workspace bytes pald_cohesion_batched needs with this plan. */
+size_t pald_batch_workspace_bytes(const pald_batch_plan *plan);
+
+/* Total packed elements sum n_i^2 (so callers can size D/U/C). */
+int64_t pald_batch_total_elements(const pald_batch_plan *plan);
+
+/* Element offset of matrix i in the packed arrays, or -1 if i is out of range. */
+int64_t pald_batch_offset(const pald_batch_plan *plan, int32_t i);
+
+/*
+ * Runs the whole batch: U_packed (may be NULL) and C_packed from D_packed.
+ * Enqueues a counter reset and one persistent kernel on `stream`; both are
+ * capturable into a hipGraph (no allocation, no memset node).
+ */
+pald_status pald_cohesion_batched(const pald_batch_plan *plan,
+                                  const float *D_packed, int32_t *U_packed,
+                                  float *C_packed, void *ws, size_t ws_bytes,
+                                  void *stream);
+
+void pald_batch_plan_destroy(pald_batch_plan *plan);
+
+/*
+ * Device timings recorded by calls made with PALD_FLAG_TIMING since the last
+ * collect.  Waits for the recorded events, then for kernel kind k writes the
+ * summed milliseconds to total_ms[k] and the number of launches to count[k]
+ * for k < kinds, and forgets the records.  Kinds: 0 pass-1 focus sizes,
+ * 1 weight preparation, 2 pass-2 cohesion, 3 cross-chunk finalize,
+ * 4 batched persistent kernel, 5 triplet pass 1, 6 triplet pass 2,
+ * 7 triplet finalize.  Returns the number of kinds defined (8).
+ */
+int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PALD_H */

@@ -1,0 +1,335 @@
+// pald_api.hip -- host side of the libpald C ABI (declared in include/pald.h).
+//
+// Argument checking, launch planning (tile grids, z/y splits, workspace
+// layout) and kernel launches on the caller's stream.  All arithmetic of the
+// method happens in the kernels of pairwise.hpp / batched.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "pald.h"
+#include "pairwise.hpp"
+#include "batched.hpp"
+
+namespace {
+
+using namespace pald;
+
+// ---- single-matrix tile configuration -------------------------------------
+// pass 1: 128 x 128 (x,y) tiles, 8 x 8 counters per thread, 16 z rows per stage
+constexpr int P1_T = 128, P1_RX = 8, P1_RY = 8, P1_KZ = 16;
+using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
+// pass 2: 64 x 128 (x,z) tiles, 4 x 8 accumulators per thread, 16 y rows per stage
+constexpr int P2_TX = 64, P2_TZ = 128, P2_RX = 4, P2_RZ = 8, P2_KY = 16;
+using P2 = Pass2Cfg<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY>;
+
+constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---- timing records -------------------------------------------------------
+constexpr int NUM_KINDS = 8;
+struct TimingRec {
+    int kind;
+    hipEvent_t start, stop;
+};
+std::mutex g_timing_mu;
+std::vector<TimingRec> g_timing;
+
+struct ScopedTiming {
+    bool on;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ScopedTiming(bool on_, int kind_, hipStream_t s_) : on(on_), kind(kind_), s(s_) {
+        if (on) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                on = false;
+                return;
+            }
+            (void)hipEventRecord(a, s);
+        }
+    }
+    ~ScopedTiming() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        g_timing.push_back({kind, a, b});
+    }
+};
+
+// ---- options -----------------------------------------------------------------
+struct Opts {
+    int variant = PALD_VARIANT_AUTO;
+    int accum = PALD_ACC_COMPENSATED;
+    int y_chunks = 0;
+    int z_chunks = 0;
+    uint32_t flags = 0;
+};
+
+pald_status read_opts(const pald_options *o, Opts &out) {
+    out = Opts{};
+    if (!o) return PALD_OK;
+    for (int r : o->reserved)
+        if (r != 0) return PALD_ERR_UNSUPPORTED;
+    if (o->variant < PALD_VARIANT_AUTO || o->variant > PALD_VARIANT_TRIPLET) return PALD_ERR_UNSUPPORTED;
+    if (o->accum != PALD_ACC_COMPENSATED && o->accum != PALD_ACC_F64) return PALD_ERR_UNSUPPORTED;
+    if (o->y_chunks < 0 || o->z_chunks < 0) return PALD_ERR_ARG;
+    if (o->flags & ~PALD_FLAG_TIMING) return PALD_ERR_UNSUPPORTED;
+    out.variant = o->variant;
+    out.accum = o->accum;
+    out.y_chunks = o->y_chunks;
+    out.z_chunks = o->z_chunks;
+    out.flags = o->flags;
+    return PALD_OK;
+}
+
+// ---- launch planning ------------------------------------------------------
+struct Plan {
+    int64_t n = 0;
+    int64_t nb1 = 0, tiles1 = 0;  // pass-1 tile grid (upper triangle)
+    int32_t z_chunks = 1, z_per_chunk = 0;
+    int32_t nbx = 0, nbz = 0;     // pass-2 tile grid
+    int32_t y_chunks = 1, y_per_chunk = 0;
+    int64_t ldw = 0;
+    size_t off_w = 0, off_u = 0, off_part = 0, bytes = 0;
+    bool need_u_scratch = false;
+};
+
+pald_status make_plan(int64_t n, const Opts &o, Plan &p) {
+    p = Plan{};
+    p.n = n;
+    p.nb1 = ceil_div(n, P1_T);
+    p.tiles1 = p.nb1 * (p.nb1 + 1) / 2;
+    if (p.tiles1 > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    int64_t zc = o.z_chunks;
+    if (zc == 0) {
+        zc = ceil_div(TARGET_WORKGROUPS, p.tiles1);
+        zc = std::min<int64_t>(zc, std::max<int64_t>(1, n / (4 * P1_KZ)));
+    }
+    zc = std::max<int64_t>(1, std::min<int64_t>(zc, ceil_div(n, P1_KZ)));
+    p.z_per_chunk = (int32_t)(ceil_div(ceil_div(n, zc), P1_KZ) * P1_KZ);
+    p.z_chunks = (int32_t)ceil_div(n, p.z_per_chunk);
+
+    p.nbx = (int32_t)ceil_div(n, P2_TX);
+    p.nbz = (int32_t)ceil_div(n, P2_TZ);
+    const int64_t tiles2 = (int64_t)p.nbx * p.nbz;
+    if (tiles2 > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    int64_t yc = o.y_chunks;
+    if (yc == 0) {
+        yc = ceil_div(TARGET_WORKGROUPS, tiles2);
+        yc = std::min<int64_t>(yc, std::max<int64_t>(1, n / (2 * P2_KY)));
+    }
+    yc = std::max<int64_t>(1, std::min<int64_t>(yc, ceil_div(n, P2_KY)));
+    p.y_per_chunk = (int32_t)(ceil_div(ceil_div(n, yc), P2_KY) * P2_KY);
+    p.y_chunks = (int32_t)ceil_div(n, p.y_per_chunk);
+    if (p.y_chunks > 65535 || p.z_chunks > 65535) return PALD_ERR_UNSUPPORTED;
+
+    p.ldw = (int64_t)align_up((size_t)n, 64);
+    size_t off = 0;
+    p.off_w = off;
+    off = align_up(off + (size_t)n * (size_t)p.ldw * sizeof(float), ALIGN);
+    p.need_u_scratch = p.z_chunks > 1;
+    p.off_u = off;
+    if (p.need_u_scratch) off = align_up(off + (size_t)n * (size_t)n * sizeof(int32_t), ALIGN);
+    p.off_part = off;
+    if (p.y_chunks > 1) off = align_up(off + (size_t)p.y_chunks * (size_t)n * (size_t)n * sizeof(double), ALIGN);
+    p.bytes = std::max<size_t>(off, ALIGN);
+    return PALD_OK;
+}
+
+// rows of an elementwise n x n kernel are grid-strided over gridDim.y <= 65535
+inline unsigned rows_grid(int64_t n) { return (unsigned)std::min<int64_t>(n, 65535); }
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+pald_status launch_status() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PALD_OK : PALD_ERR_DEVICE;
+}
+
+// Pass 1 into (U, W); W may be null.  Returns after enqueueing.
+pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *W,
+                      int64_t ldw, const Plan &p, hipStream_t s, bool timing) {
+    const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
+    if (p.z_chunks == 1) {
+        ScopedTiming tm(timing, 0, s);
+        pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ>
+            <<<dim3((unsigned)p.tiles1, 1), P1::NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec);
+        return launch_status();
+    }
+    {
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        zero_i32_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(U, ldu, n);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    {
+        ScopedTiming tm(timing, 0, s);
+        pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1::NT, 0, s>>>(
+            D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    if (W) {
+        ScopedTiming tm(timing, 1, s);
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(U, ldu, W, ldw, n);
+        return launch_status();
+    }
+    return PALD_OK;
+}
+
+pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, int64_t ldw, float *C,
+                      int64_t ldc, double *part, const Plan &p, bool f64, hipStream_t s, bool timing) {
+    const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
+    const int vecw = (aligned16(W) && ldw % 4 == 0) ? 1 : 0;
+    const dim3 grid((unsigned)((int64_t)p.nbx * p.nbz), (unsigned)p.y_chunks);
+    {
+        ScopedTiming tm(timing, 2, s);
+        if (f64)
+            pass2_cohesion_kernel<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY, true>
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.nbx, p.y_per_chunk, vecd, vecw);
+        else
+            pass2_cohesion_kernel<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY, false>
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.nbx, p.y_per_chunk, vecd, vecw);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    if (p.y_chunks > 1) {
+        ScopedTiming tm(timing, 3, s);
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        finalize_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(part, p.y_chunks, n, C, ldc);
+        return launch_status();
+    }
+    return PALD_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char *pald_status_string(int32_t s) {
+    switch (s) {
+    case PALD_OK: return "ok";
+    case PALD_ERR_ARG: return "invalid argument";
+    case PALD_ERR_INPUT: return "invalid input data";
+    case PALD_ERR_DEVICE: return "device or launch error";
+    case PALD_ERR_NOMEM: return "out of memory";
+    case PALD_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+    }
+}
+
+int32_t pald_version(void) { return 10000 * 0 + 100 * 1 + 0; }
+
+size_t pald_workspace_bytes(int64_t n, const pald_options *opt) {
+    Opts o;
+    if (n < 2 || read_opts(opt, o) != PALD_OK) return 0;
+    if (o.variant == PALD_VARIANT_TRIPLET) return triplet_workspace_bytes(n);
+    Plan p;
+    if (make_plan(n, o, p) != PALD_OK) return 0;
+    return p.bytes;
+}
+
+pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, void *stream,
+                             const pald_options *opt) {
+    Opts o;
+    if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
+    if (!D || !U || n < 2 || ldd < n || ldu < n) return PALD_ERR_ARG;
+    Plan p;
+    if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
+    return run_pass1(D, n, ldd, U, ldu, nullptr, p.ldw, p, (hipStream_t)stream, (o.flags & PALD_FLAG_TIMING) != 0);
+}
+
+pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
+                          void *ws, size_t ws_bytes, void *stream, const pald_options *opt) {
+    Opts o;
+    if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
+    if (!D || !C || !ws || n < 2 || ldd < n || ldc < n || (U && ldu < n)) return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
+    if (o.variant == PALD_VARIANT_TRIPLET)
+        return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, o.accum == PALD_ACC_F64, timing);
+    Plan p;
+    if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
+    if (ws_bytes < p.bytes) return PALD_ERR_ARG;
+    char *base = static_cast<char *>(ws);
+    float *W = reinterpret_cast<float *>(base + p.off_w);
+    int32_t *Ub = U;
+    int64_t ldub = ldu;
+    if (!Ub && p.need_u_scratch) {
+        Ub = reinterpret_cast<int32_t *>(base + p.off_u);
+        ldub = n;
+    }
+    if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, p.ldw, p, s, timing); st != PALD_OK) return st;
+    double *part = p.y_chunks > 1 ? reinterpret_cast<double *>(base + p.off_part) : nullptr;
+    return run_pass2(D, n, ldd, W, p.ldw, C, ldc, part, p, o.accum == PALD_ACC_F64, s, timing);
+}
+
+pald_status pald_check_input(const float *D, int64_t n, int64_t ldd, void *ws, size_t ws_bytes, void *stream,
+                             uint32_t *flags_out) {
+    if (!D || !ws || n < 2 || ldd < n || ws_bytes < 256) return PALD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *flag = static_cast<uint32_t *>(ws);
+    zero_i32_kernel<<<dim3(1, 1), 64, 0, s>>>(reinterpret_cast<int32_t *>(flag), 1, 1);
+    if (launch_status() != PALD_OK) return PALD_ERR_DEVICE;
+    const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+    check_input_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(D, n, ldd, flag);
+    if (launch_status() != PALD_OK) return PALD_ERR_DEVICE;
+    uint32_t h = 0;
+    if (hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) return PALD_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return PALD_ERR_DEVICE;
+    if (flags_out) *flags_out = h;
+    return h ? PALD_ERR_INPUT : PALD_OK;
+}
+
+int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds) {
+    std::vector<TimingRec> recs;
+    {
+        std::lock_guard<std::mutex> g(g_timing_mu);
+        recs.swap(g_timing);
+    }
+    for (int32_t k = 0; k < kinds && k < NUM_KINDS; ++k) {
+        if (total_ms) total_ms[k] = 0.0;
+        if (count) count[k] = 0;
+    }
+    for (auto &r : recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess &&
+            r.kind < kinds) {
+            if (total_ms) total_ms[r.kind] += ms;
+            if (count) count[r.kind] += 1;
+        }
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    return NUM_KINDS;
+}
+
+}  // extern "C"
+
+// ---- batched mode (not implemented yet) ------------------------------------
+struct pald_batch_plan {
+    int32_t count;
+};
+
+extern "C" {
+pald_status pald_batch_plan_create(int32_t, const int64_t *, const pald_options *, pald_batch_plan **plan_out) {
+    if (plan_out) *plan_out = nullptr;
+    return PALD_ERR_UNSUPPORTED;
+}
+size_t pald_batch_workspace_bytes(const pald_batch_plan *) { return 0; }
+int64_t pald_batch_total_elements(const pald_batch_plan *) { return 0; }
+int64_t pald_batch_offset(const pald_batch_plan *, int32_t) { return -1; }
+pald_status pald_cohesion_batched(const pald_batch_plan *, const float *, int32_t *, float *, void *, size_t,
+                                  void *) {
+    return PALD_ERR_UNSUPPORTED;
+}
+void pald_batch_plan_destroy(pald_batch_plan *) {}
+}

@@ -1,0 +1,285 @@
+"""Python binding of libpald (ctypes over the C ABI in include/pald.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libpald.so.  PyTorch supplies device memory (tensors) and the
+stream (`torch.cuda.current_stream()`); nothing here computes PaLD.
+
+If libpald.so is missing or cannot be loaded, every call raises -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpald.so")
+
+OK, ERR_ARG, ERR_INPUT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = range(6)
+VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2}
+ACCUMS = {"compensated": 0, "f64": 1}
+FLAG_TIMING = 1
+TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
+                "triplet_pass1", "triplet_pass2", "triplet_finalize")
+INPUT_FLAGS = {1: "nan", 2: "inf", 4: "negative", 8: "asymmetric", 16: "nonzero_diagonal"}
+
+#: every symbol include/pald.h declares
+EXPORTED = (
+    "pald_status_string", "pald_version", "pald_workspace_bytes", "pald_focus_sizes",
+    "pald_cohesion", "pald_check_input", "pald_batch_plan_create", "pald_batch_workspace_bytes",
+    "pald_batch_total_elements", "pald_batch_offset", "pald_cohesion_batched",
+    "pald_batch_plan_destroy", "pald_timings_collect",
+)
+
+
+class PaldError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("accum", ctypes.c_int32),
+        ("y_chunks", ctypes.c_int32),
+        ("z_chunks", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libpald.so (built by paper_2307_16652_amd.build); raises if it is absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2307_16652_amd.build`")
+    lib = ctypes.CDLL(p)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    opt = ctypes.POINTER(Options)
+    lib.pald_status_string.argtypes = [i32]
+    lib.pald_status_string.restype = ctypes.c_char_p
+    lib.pald_version.argtypes = []
+    lib.pald_version.restype = i32
+    lib.pald_workspace_bytes.argtypes = [i64, opt]
+    lib.pald_workspace_bytes.restype = sz
+    lib.pald_focus_sizes.argtypes = [vp, i64, i64, vp, i64, vp, opt]
+    lib.pald_focus_sizes.restype = i32
+    lib.pald_cohesion.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, sz, vp, opt]
+    lib.pald_cohesion.restype = i32
+    lib.pald_check_input.argtypes = [vp, i64, i64, vp, sz, vp, ctypes.POINTER(ctypes.c_uint32)]
+    lib.pald_check_input.restype = i32
+    lib.pald_batch_plan_create.argtypes = [i32, ctypes.POINTER(i64), opt, ctypes.POINTER(vp)]
+    lib.pald_batch_plan_create.restype = i32
+    lib.pald_batch_workspace_bytes.argtypes = [vp]
+    lib.pald_batch_workspace_bytes.restype = sz
+    lib.pald_batch_total_elements.argtypes = [vp]
+    lib.pald_batch_total_elements.restype = i64
+    lib.pald_batch_offset.argtypes = [vp, i32]
+    lib.pald_batch_offset.restype = i64
+    lib.pald_cohesion_batched.argtypes = [vp, vp, vp, vp, vp, sz, vp]
+    lib.pald_cohesion_batched.restype = i32
+    lib.pald_batch_plan_destroy.argtypes = [vp]
+    lib.pald_batch_plan_destroy.restype = None
+    lib.pald_timings_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
+    lib.pald_timings_collect.restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load_library().pald_status_string(int(status)).decode()
+    except Exception:  # pragma: no cover - library missing
+        return f"status {status}"
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise PaldError(status, where)
+
+
+def make_options(variant: str = "auto", accum: str = "compensated", y_chunks: int = 0,
+                 z_chunks: int = 0, timing: bool = False) -> Options:
+    o = Options()
+    o.variant = VARIANTS[variant]
+    o.accum = ACCUMS[accum]
+    o.y_chunks = int(y_chunks)
+    o.z_chunks = int(z_chunks)
+    o.flags = FLAG_TIMING if timing else 0
+    return o
+
+
+# ----------------------------------------------------------------------------
+# torch-facing helpers (torch is imported lazily: only memory and streams)
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_matrix(D):
+    torch = _torch()
+    if not isinstance(D, torch.Tensor) or not D.is_cuda:
+        raise TypeError("D must be a torch tensor on a HIP (cuda) device")
+    if D.dtype != torch.float32 or D.dim() != 2 or D.shape[0] != D.shape[1]:
+        raise ValueError("D must be a square float32 matrix")
+    if D.stride(1) != 1 or D.stride(0) < D.shape[0]:
+        raise ValueError("D must be row-major with unit column stride")
+    return D.shape[0], D.stride(0)
+
+
+def workspace_bytes(n: int, **opts) -> int:
+    o = make_options(**opts)
+    return int(load_library().pald_workspace_bytes(int(n), ctypes.byref(o)))
+
+
+def workspace(n: int, device, **opts):
+    torch = _torch()
+    nbytes = workspace_bytes(n, **opts)
+    if nbytes == 0:
+        raise PaldError(ERR_ARG, "pald_workspace_bytes")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def focus_sizes(D, *, z_chunks: int = 0, timing: bool = False, out=None):
+    """U (int32, n x n): local focus sizes of distance matrix D."""
+    torch = _torch()
+    n, ldd = _check_matrix(D)
+    U = out if out is not None else torch.empty((n, n), dtype=torch.int32, device=D.device)
+    o = make_options(z_chunks=z_chunks, timing=timing)
+    st = load_library().pald_focus_sizes(D.data_ptr(), n, ldd, U.data_ptr(), U.stride(0),
+                                         _stream_ptr(D.device), ctypes.byref(o))
+    _check(st, "pald_focus_sizes")
+    return U
+
+
+def cohesion(D, *, variant: str = "auto", accum: str = "compensated", y_chunks: int = 0,
+             z_chunks: int = 0, want_u: bool = True, timing: bool = False, ws=None,
+             out_u=None, out_c=None):
+    """(U, C): focus sizes (int32, or None if want_u is False) and cohesion (float32)."""
+    torch = _torch()
+    n, ldd = _check_matrix(D)
+    opts = dict(variant=variant, accum=accum, y_chunks=y_chunks, z_chunks=z_chunks, timing=timing)
+    o = make_options(**opts)
+    if ws is None:
+        ws = workspace(n, D.device, **opts)
+    U = None
+    if want_u:
+        U = out_u if out_u is not None else torch.empty((n, n), dtype=torch.int32, device=D.device)
+    C = out_c if out_c is not None else torch.empty((n, n), dtype=torch.float32, device=D.device)
+    st = load_library().pald_cohesion(
+        D.data_ptr(), n, ldd,
+        U.data_ptr() if U is not None else None, U.stride(0) if U is not None else 0,
+        C.data_ptr(), C.stride(0), ws.data_ptr(), ws.numel(),
+        _stream_ptr(D.device), ctypes.byref(o))
+    _check(st, "pald_cohesion")
+    return U, C
+
+
+def check_input(D) -> list[str]:
+    """Names of the input-contract violations found in D (empty list if valid)."""
+    torch = _torch()
+    n, ldd = _check_matrix(D)
+    ws = torch.empty(256, dtype=torch.uint8, device=D.device)
+    flags = ctypes.c_uint32(0)
+    st = load_library().pald_check_input(D.data_ptr(), n, ldd, ws.data_ptr(), ws.numel(),
+                                         _stream_ptr(D.device), ctypes.byref(flags))
+    if st not in (OK, ERR_INPUT):
+        _check(st, "pald_check_input")
+    return [name for bit, name in INPUT_FLAGS.items() if flags.value & bit]
+
+
+def timings_collect() -> dict:
+    """{kernel kind: (total ms, launches)} recorded by calls made with timing=True."""
+    k = len(TIMING_KINDS)
+    tot = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    load_library().pald_timings_collect(tot, cnt, k)
+    return {name: (tot[i], cnt[i]) for i, name in enumerate(TIMING_KINDS) if cnt[i]}
+
+
+# ----------------------------------------------------------------------------
+# batched mode
+
+
+class BatchPlan:
+    """Plan for one packed batch of matrices of sizes `sizes` (see pald.h)."""
+
+    def __init__(self, sizes: Sequence[int], **opts):
+        lib = load_library()
+        self.sizes = [int(s) for s in sizes]
+        arr = (ctypes.c_int64 * len(self.sizes))(*self.sizes)
+        o = make_options(**opts)
+        h = ctypes.c_void_p()
+        st = lib.pald_batch_plan_create(len(self.sizes), arr, ctypes.byref(o), ctypes.byref(h))
+        _check(st, "pald_batch_plan_create")
+        self._h = h
+        self._lib = lib
+        self.total = int(lib.pald_batch_total_elements(h))
+        self.offsets = [int(lib.pald_batch_offset(h, i)) for i in range(len(self.sizes))]
+        self.ws_bytes = int(lib.pald_batch_workspace_bytes(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pald_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device):
+        return _torch().empty(max(self.ws_bytes, 256), dtype=_torch().uint8, device=device)
+
+    def run(self, D_packed, U_packed=None, C_packed=None, ws=None, want_u: bool = True):
+        torch = _torch()
+        if D_packed.dtype != torch.float32 or D_packed.numel() != self.total or not D_packed.is_cuda:
+            raise ValueError("D_packed must be a flat float32 cuda tensor of sum(n_i^2) elements")
+        dev = D_packed.device
+        if want_u and U_packed is None:
+            U_packed = torch.empty(self.total, dtype=torch.int32, device=dev)
+        if C_packed is None:
+            C_packed = torch.empty(self.total, dtype=torch.float32, device=dev)
+        if ws is None:
+            ws = self.workspace(dev)
+        st = self._lib.pald_cohesion_batched(
+            self._h, D_packed.data_ptr(), U_packed.data_ptr() if U_packed is not None else None,
+            C_packed.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev))
+        _check(st, "pald_cohesion_batched")
+        return U_packed, C_packed
+
+    def pack(self, mats):
+        torch = _torch()
+        return torch.cat([m.reshape(-1) for m in mats])
+
+    def unpack(self, flat):
+        return [flat[o:o + s * s].view(s, s) for o, s in zip(self.offsets, self.sizes)]
+
+
+def cohesion_batched(mats, **opts):
+    """[(U_i, C_i)] for a list of square float32 cuda matrices, in one batched launch."""
+    plan = BatchPlan([m.shape[0] for m in mats], **opts)
+    try:
+        Dp = plan.pack(mats)
+        Up, Cp = plan.run(Dp)
+        return list(zip(plan.unpack(Up), plan.unpack(Cp)))
+    finally:
+        plan.close()

@@ -1,0 +1,108 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol,
+and rejects bad arguments synchronously before any device work (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2307_16652_amd import pald
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pald.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pald_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_what_the_binding_expects():
+    assert declared_functions() == sorted(pald.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pald.LIB_PATH)
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, f"missing exports: {missing}"
+
+
+def test_status_strings_and_version():
+    lib = pald.load_library()
+    assert lib.pald_status_string(0) == b"ok"
+    assert lib.pald_status_string(99) == b"unknown status"
+    assert lib.pald_version() >= 100
+
+
+def test_workspace_sizes():
+    assert pald.workspace_bytes(1) == 0
+    small = pald.workspace_bytes(100)
+    big = pald.workspace_bytes(16384)
+    assert small >= 100 * 100 * 4 and big >= 16384 * 16384 * 4
+    assert big % 256 == 0
+    # a forced y split needs float64 partials
+    assert pald.workspace_bytes(1000, y_chunks=4) >= 4 * 1000 * 1000 * 8
+
+
+def _opts(**kw):
+    return ctypes.byref(pald.make_options(**kw))
+
+
+@pytest.mark.parametrize("n,ldd,ldc", [(1, 1, 1), (0, 4, 4), (8, 7, 8), (8, 8, 7)])
+def test_cohesion_bad_sizes(n, ldd, ldc):
+    lib = pald.load_library()
+    fake = ctypes.c_void_p(0x10000)
+    st = lib.pald_cohesion(fake, n, ldd, None, 0, fake, ldc, fake, 1 << 20, None, _opts())
+    assert st == pald.ERR_ARG
+
+
+def test_cohesion_null_pointers_and_small_workspace():
+    lib = pald.load_library()
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.pald_cohesion(None, 8, 8, None, 0, fake, 8, fake, 1 << 20, None, _opts()) == pald.ERR_ARG
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, None, 8, fake, 1 << 20, None, _opts()) == pald.ERR_ARG
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, None, 1 << 20, None, _opts()) == pald.ERR_ARG
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, fake, 16, None, _opts()) == pald.ERR_ARG
+    # misaligned workspace
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, ctypes.c_void_p(0x10004), 1 << 20, None,
+                             _opts()) == pald.ERR_ARG
+    # U given with a too-small leading dimension
+    assert lib.pald_cohesion(fake, 8, 8, fake, 4, fake, 8, fake, 1 << 20, None, _opts()) == pald.ERR_ARG
+
+
+def test_unknown_options_rejected():
+    lib = pald.load_library()
+    fake = ctypes.c_void_p(0x10000)
+    o = pald.make_options()
+    o.reserved[1] = 3
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, fake, 1 << 20, None, ctypes.byref(o)) == \
+        pald.ERR_UNSUPPORTED
+    o = pald.make_options()
+    o.accum = 7
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, fake, 1 << 20, None, ctypes.byref(o)) == \
+        pald.ERR_UNSUPPORTED
+    o = pald.make_options()
+    o.flags = 0x80
+    assert lib.pald_focus_sizes(fake, 8, 8, fake, 8, None, ctypes.byref(o)) == pald.ERR_UNSUPPORTED
+    o = pald.make_options()
+    o.y_chunks = -1
+    assert lib.pald_workspace_bytes(8, ctypes.byref(o)) == 0
+
+
+def test_focus_sizes_and_check_input_bad_args():
+    lib = pald.load_library()
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.pald_focus_sizes(None, 8, 8, fake, 8, None, None) == pald.ERR_ARG
+    assert lib.pald_focus_sizes(fake, 8, 8, None, 8, None, None) == pald.ERR_ARG
+    assert lib.pald_focus_sizes(fake, 8, 8, fake, 7, None, None) == pald.ERR_ARG
+    assert lib.pald_check_input(fake, 8, 8, fake, 8, None, None) == pald.ERR_ARG
+    assert lib.pald_check_input(fake, 1, 1, fake, 256, None, None) == pald.ERR_ARG
+
+
+def test_timings_collect_without_records():
+    lib = pald.load_library()
+    tot = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_int64 * 8)()
+    assert lib.pald_timings_collect(tot, cnt, 8) == 8
+    assert list(cnt) == [0] * 8

@@ -13,9 +13,11 @@ point in each of the two defining sums) divided by the time per step.
 
 `roofline` describes the dominant kernel (pass 2, cohesion), whose launches
 are timed with HIP events on the stream they run on.  Its algorithmic work is
-6 VALU lane-operations per (x, y, z) term with y != x (one min, two compares,
-two selects, one add) = 6 n^2 (n-1) per launch, set against the VALU issue
-peak of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s.
+5 VALU lane-operations per cohesion term (x, y, z), y != x: for an unordered
+pair {x, z} and a second point y the two terms of c_xz and c_zx need one min,
+three compares, four selects and two adds, i.e. 10 operations for 2 terms;
+5 n^2 (n-1) per launch.  It is set against the VALU issue peak of
+256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s.
 
 `cpu_baseline` is the FP64 oracle on the host cores for a bounded sample of
 rows of the same matrix (2 n^2 comparison terms per row).
@@ -37,7 +39,7 @@ if ROOT not in sys.path:
 N = 16384
 SEED = 3
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3216 T lane-ops/s
-PASS2_OPS_PER_TERM = 6
+PASS2_OPS_PER_TERM = 5
 PASS1_OPS_PER_TERM = 3
 
 
@@ -83,6 +85,9 @@ def main():
     ap.add_argument("--n", type=int, default=N, help="matrix size (default 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain elementwise kernel that reads and writes 1 GiB, so a "
+                         "counter profile can scale FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -105,6 +110,14 @@ def main():
 
     n = args.n
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        progress("copy calibration: one elementwise kernel, 1 GiB read + 1 GiB written")
+        del src, dst
     progress(f"generating grid3d n={n} seed={SEED}")
     D = synth.grid3d(n=n, seed=SEED)
     Dg = torch.from_numpy(D).to(dev)

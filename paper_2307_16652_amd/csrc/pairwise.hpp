@@ -38,6 +38,150 @@ __device__ __forceinline__ uint32_t key_of(float d) { return __float_as_uint(d) 
 
 __device__ __forceinline__ uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
 
+// Per-lane condition -> 64-lane mask in a scalar register pair, and back.
+// Combining compare results as masks with scalar instructions keeps vector
+// selects from waiting on a mask written by the preceding vector instruction.
+// Only used where every lane of the wave is active.
+__device__ __forceinline__ uint64_t lane_mask(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Focus counting for one x and eight y: c[j] += [min(x, y[j]) <= a[j]].
+// Written as one block so that each compare mask is read by its v_addc (as the
+// carry-in) seven instructions after it is written, which covers the wait
+// states a vector read of a vector-written scalar register needs; the
+// compiler's own schedule puts every compare into VCC and pads each one with
+// s_nop.  Registers only, no memory access.
+__device__ __forceinline__ void focus_count8(int32_t (&c)[8], uint32_t x, const uint32_t (&y)[8],
+                                             const uint32_t (&a)[8]) {
+    uint32_t m0, m1, m2, m3, m4, m5, m6, m7;
+    uint64_t k0, k1, k2, k3, k4, k5, k6, k7, co;
+    asm("v_min_u32 %[m0], %[x], %[y0]\n\t"
+        "v_min_u32 %[m1], %[x], %[y1]\n\t"
+        "v_min_u32 %[m2], %[x], %[y2]\n\t"
+        "v_min_u32 %[m3], %[x], %[y3]\n\t"
+        "v_min_u32 %[m4], %[x], %[y4]\n\t"
+        "v_min_u32 %[m5], %[x], %[y5]\n\t"
+        "v_min_u32 %[m6], %[x], %[y6]\n\t"
+        "v_min_u32 %[m7], %[x], %[y7]\n\t"
+        "v_cmp_le_u32_e64 %[k0], %[m0], %[a0]\n\t"
+        "v_cmp_le_u32_e64 %[k1], %[m1], %[a1]\n\t"
+        "v_cmp_le_u32_e64 %[k2], %[m2], %[a2]\n\t"
+        "v_cmp_le_u32_e64 %[k3], %[m3], %[a3]\n\t"
+        "v_cmp_le_u32_e64 %[k4], %[m4], %[a4]\n\t"
+        "v_cmp_le_u32_e64 %[k5], %[m5], %[a5]\n\t"
+        "v_cmp_le_u32_e64 %[k6], %[m6], %[a6]\n\t"
+        "v_cmp_le_u32_e64 %[k7], %[m7], %[a7]\n\t"
+        "v_addc_co_u32_e64 %[c0], %[co], 0, %[c0], %[k0]\n\t"
+        "v_addc_co_u32_e64 %[c1], %[co], 0, %[c1], %[k1]\n\t"
+        "v_addc_co_u32_e64 %[c2], %[co], 0, %[c2], %[k2]\n\t"
+        "v_addc_co_u32_e64 %[c3], %[co], 0, %[c3], %[k3]\n\t"
+        "v_addc_co_u32_e64 %[c4], %[co], 0, %[c4], %[k4]\n\t"
+        "v_addc_co_u32_e64 %[c5], %[co], 0, %[c5], %[k5]\n\t"
+        "v_addc_co_u32_e64 %[c6], %[co], 0, %[c6], %[k6]\n\t"
+        "v_addc_co_u32_e64 %[c7], %[co], 0, %[c7], %[k7]"
+        : [c0] "+v"(c[0]), [c1] "+v"(c[1]), [c2] "+v"(c[2]), [c3] "+v"(c[3]), [c4] "+v"(c[4]),
+          [c5] "+v"(c[5]), [c6] "+v"(c[6]), [c7] "+v"(c[7]), [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2),
+          [m3] "=&v"(m3), [m4] "=&v"(m4), [m5] "=&v"(m5), [m6] "=&v"(m6), [m7] "=&v"(m7), [k0] "=&s"(k0),
+          [k1] "=&s"(k1), [k2] "=&s"(k2), [k3] "=&s"(k3), [k4] "=&s"(k4), [k5] "=&s"(k5), [k6] "=&s"(k6),
+          [k7] "=&s"(k7), [co] "=&s"(co)
+        : [x] "v"(x), [y0] "v"(y[0]), [y1] "v"(y[1]), [y2] "v"(y[2]), [y3] "v"(y[3]), [y4] "v"(y[4]),
+          [y5] "v"(y[5]), [y6] "v"(y[6]), [y7] "v"(y[7]), [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]),
+          [a3] "v"(a[3]), [a4] "v"(a[4]), [a5] "v"(a[5]), [a6] "v"(a[6]), [a7] "v"(a[7]));
+}
+
+// Cohesion terms of one x and four z for one second point y, both directions:
+//   in_j  = [t_j <= min(a, b_j)]
+//   rf_j (+)= in_j ? (t_j < b_j ? wx : whx) : 0          (c_xz, focus of x and y)
+//   rr_j (+)= in_j ? (t_j < a   ? wz_j : whz_j) : 0      (c_zx, focus of z and y)
+// with a = d_xy, b_j = d_z_j y, t_j = d_x z_j (all as keys), wx = W_xy,
+// wz_j = W_z_j y and wh = w / 2.  ASSIGN starts new runs (rf = term) instead of
+// adding.  One block, so that every compare mask is read at least two
+// instructions after it is written (the wait states a vector read of a
+// vector-written scalar register needs) and the four pairs interleave; the
+// compiler's own schedule funnels the masks through one or two registers.
+// Registers only, no memory access.
+template <bool ASSIGN>
+__device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], const uint32_t (&t)[4], uint32_t a,
+                                                const uint32_t (&b)[4], float wx, float whx, const float (&wz)[4],
+                                                const float (&whz)[4]) {
+    uint32_t m0, m1, m2, m3;
+    float f0, f1, f2, f3, g0, g1, g2, g3;
+    uint64_t i0, i1, i2, i3, p0, p1, p2, p3, q0, q1, q2, q3;
+#define PALD_T4_HEAD                                                                                            \
+    "v_min_u32 %[m0], %[a], %[b0]\n\t"                                                                          \
+    "v_min_u32 %[m1], %[a], %[b1]\n\t"                                                                          \
+    "v_min_u32 %[m2], %[a], %[b2]\n\t"                                                                          \
+    "v_min_u32 %[m3], %[a], %[b3]\n\t"                                                                          \
+    "v_cmp_lt_u32_e64 %[p0], %[t0], %[b0]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[q0], %[t0], %[a]\n\t"                                                                   \
+    "v_cmp_le_u32_e64 %[i0], %[t0], %[m0]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[p1], %[t1], %[b1]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[q1], %[t1], %[a]\n\t"                                                                   \
+    "v_cmp_le_u32_e64 %[i1], %[t1], %[m1]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[p2], %[t2], %[b2]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[q2], %[t2], %[a]\n\t"                                                                   \
+    "v_cmp_le_u32_e64 %[i2], %[t2], %[m2]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[p3], %[t3], %[b3]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[q3], %[t3], %[a]\n\t"                                                                   \
+    "v_cmp_le_u32_e64 %[i3], %[t3], %[m3]\n\t"                                                                  \
+    "v_cndmask_b32_e64 %[f0], %[whx], %[wx], %[p0]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g0], %[whz0], %[wz0], %[q0]\n\t"                                                       \
+    "v_cndmask_b32_e64 %[f1], %[whx], %[wx], %[p1]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g1], %[whz1], %[wz1], %[q1]\n\t"                                                       \
+    "v_cndmask_b32_e64 %[f2], %[whx], %[wx], %[p2]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g2], %[whz2], %[wz2], %[q2]\n\t"                                                       \
+    "v_cndmask_b32_e64 %[f3], %[whx], %[wx], %[p3]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g3], %[whz3], %[wz3], %[q3]\n\t"
+#define PALD_T4_OPERANDS                                                                                        \
+    [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3), [f0] "=&v"(f0), [f1] "=&v"(f1),          \
+        [f2] "=&v"(f2), [f3] "=&v"(f3), [g0] "=&v"(g0), [g1] "=&v"(g1), [g2] "=&v"(g2), [g3] "=&v"(g3),       \
+        [i0] "=&s"(i0), [i1] "=&s"(i1), [i2] "=&s"(i2), [i3] "=&s"(i3), [p0] "=&s"(p0), [p1] "=&s"(p1),       \
+        [p2] "=&s"(p2), [p3] "=&s"(p3), [q0] "=&s"(q0), [q1] "=&s"(q1), [q2] "=&s"(q2), [q3] "=&s"(q3)
+#define PALD_T4_INPUTS                                                                                          \
+    [t0] "v"(t[0]), [t1] "v"(t[1]), [t2] "v"(t[2]), [t3] "v"(t[3]), [a] "v"(a), [b0] "v"(b[0]),               \
+        [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3]), [wx] "v"(wx), [whx] "v"(whx), [wz0] "v"(wz[0]),       \
+        [wz1] "v"(wz[1]), [wz2] "v"(wz[2]), [wz3] "v"(wz[3]), [whz0] "v"(whz[0]), [whz1] "v"(whz[1]),         \
+        [whz2] "v"(whz[2]), [whz3] "v"(whz[3])
+    if (ASSIGN) {
+        asm(PALD_T4_HEAD
+            "v_cndmask_b32_e64 %[rf0], 0, %[f0], %[i0]\n\t"
+            "v_cndmask_b32_e64 %[rr0], 0, %[g0], %[i0]\n\t"
+            "v_cndmask_b32_e64 %[rf1], 0, %[f1], %[i1]\n\t"
+            "v_cndmask_b32_e64 %[rr1], 0, %[g1], %[i1]\n\t"
+            "v_cndmask_b32_e64 %[rf2], 0, %[f2], %[i2]\n\t"
+            "v_cndmask_b32_e64 %[rr2], 0, %[g2], %[i2]\n\t"
+            "v_cndmask_b32_e64 %[rf3], 0, %[f3], %[i3]\n\t"
+            "v_cndmask_b32_e64 %[rr3], 0, %[g3], %[i3]"
+            : [rf0] "=&v"(rf[0]), [rf1] "=&v"(rf[1]), [rf2] "=&v"(rf[2]), [rf3] "=&v"(rf[3]),
+              [rr0] "=&v"(rr[0]), [rr1] "=&v"(rr[1]), [rr2] "=&v"(rr[2]), [rr3] "=&v"(rr[3]), PALD_T4_OPERANDS
+            : PALD_T4_INPUTS);
+    } else {
+        asm(PALD_T4_HEAD
+            "v_cndmask_b32_e64 %[f0], 0, %[f0], %[i0]\n\t"
+            "v_cndmask_b32_e64 %[g0], 0, %[g0], %[i0]\n\t"
+            "v_cndmask_b32_e64 %[f1], 0, %[f1], %[i1]\n\t"
+            "v_cndmask_b32_e64 %[g1], 0, %[g1], %[i1]\n\t"
+            "v_cndmask_b32_e64 %[f2], 0, %[f2], %[i2]\n\t"
+            "v_cndmask_b32_e64 %[g2], 0, %[g2], %[i2]\n\t"
+            "v_cndmask_b32_e64 %[f3], 0, %[f3], %[i3]\n\t"
+            "v_cndmask_b32_e64 %[g3], 0, %[g3], %[i3]\n\t"
+            "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
+            "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
+            "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
+            "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
+            "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
+            "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
+            "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
+            "v_add_f32 %[rr3], %[rr3], %[g3]"
+            : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
+              [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), PALD_T4_OPERANDS
+            : PALD_T4_INPUTS);
+    }
+#undef PALD_T4_HEAD
+#undef PALD_T4_OPERANDS
+#undef PALD_T4_INPUTS
+}
+
 // Upper-triangular tile enumeration: k -> (bx, by) with bx <= by, by-major.
 __device__ __forceinline__ void tri_tile(int32_t k, int32_t &bx, int32_t &by) {
     int32_t r = (int32_t)((sqrtf(8.0f * (float)k + 1.0f) - 1.0f) * 0.5f);
@@ -108,6 +252,7 @@ struct Pass1Cfg {
     static constexpr int VEC_PER_THREAD = VEC_PER_CHUNK / NT;
     static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(T % 4 == 0, "tile must be a multiple of 4");
+    static_assert(RY == 8, "focus counting works on rows of 8 y");
 };
 
 template <int T, int RX, int RY, int KZ>
@@ -178,9 +323,7 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
 #pragma unroll
             for (int j = 0; j < RY; ++j) ys[j] = s[z * Cfg::ROW + T + ty * RY + j];
 #pragma unroll
-            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                for (int j = 0; j < RY; ++j) cnt[i][j] += (umin(xs[i], ys[j]) <= a[i][j]) ? 1 : 0;
+            for (int i = 0; i < RX; ++i) focus_count8(cnt[i], xs[i], ys, a[i]);
         }
         if (c + 1 < nchunks) stash(buf ^ 1);
         __syncthreads();
@@ -233,69 +376,84 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: cohesion.
+// Pass 2: cohesion, both directions of every pair {x, z} at once.
 //
-// Grid: blockIdx.x = bx + nbx * bz over (x,z) tiles of TXx x TZ; blockIdx.y is
-// the y-chunk.  With one y-chunk the tile writes C = fl32(sum / (n-1))
-// directly; otherwise it writes its float64 partial sum to
+// For a pair (x, z) and a second point y, the term of c_xz (focus of x and y,
+// third point z) and the term of c_zx (focus of z and y, third point x) read
+// the same three distances t = d_xz, a = d_xy, b = d_zy, and both vanish
+// unless t <= min(a, b):
+//     c_xz += [t <= min(a,b)] * (t < b ? W_xy : W_xy / 2)
+//     c_zx += [t <= min(a,b)] * (t < a ? W_zy : W_zy / 2)
+// One thread keeps both accumulators of its pairs and shares the membership
+// test between them.
+//
+// Grid: blockIdx.x enumerates the upper-triangular T x T tiles (bx <= bz);
+// blockIdx.y is the y-chunk.  A tile with bx < bz writes C[X][Z] and C[Z][X];
+// a diagonal tile covers every ordered pair of its block once as (x, z) and
+// writes only C[x][z].  With one y-chunk the tile writes
+// C = fl32(sum / (n-1)); otherwise it writes float64 partial sums
 // partial[chunk][x][z] (ld n) for finalize_kernel.
 //
-// Per y the tile needs row y of D restricted to the x and z ranges (a = d_yx,
-// b = d_yz; D symmetric) and row y of W restricted to x (W_yx = W_xy).
-// Rows y >= n, and rows past the chunk, stage W = 0 and so add nothing; the
-// term y = x adds nothing because W_xx = 0.
+// Per y the tile stages row y of D and of W restricted to the x range and to
+// the z range (a = d_yx, b = d_yz, W_yx, W_yz; D and W are symmetric).  Rows
+// y >= n, and rows past the chunk, stage W = 0 and so add nothing; the terms
+// y = x and y = z add nothing because W_xx = W_zz = 0.
+//
+// The compare results are combined as 64-lane masks with scalar instructions
+// (s_and), so no vector select waits on a mask written by the vector
+// instruction just before it.
 
-template <int TXx, int TZ, int RX, int RZ, int KY>
+template <int T, int R, int KY>
 struct Pass2Cfg {
-    static constexpr int TX = TXx / RX;
-    static constexpr int TZt = TZ / RZ;
-    static constexpr int NT = TX * TZt;
-    static constexpr int ROW = 2 * TXx + TZ;            // a keys | W values | b keys
+    static constexpr int TT = T / R;                    // threads along each side
+    static constexpr int NT = TT * TT;
+    static constexpr int ROW = 4 * T;                   // a | W_yx | b | W_yz
     static constexpr int VEC_PER_CHUNK = KY * ROW / 4;
     static constexpr int VEC_PER_THREAD = VEC_PER_CHUNK / NT;
     static constexpr int RUN = 8;                       // float32 run length before a Kahan fold
     static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(KY % RUN == 0, "KY must be a multiple of the run length");
-    static_assert(TXx % 4 == 0 && TZ % 4 == 0, "tile sides must be multiples of 4");
+    static_assert(T % 4 == 0, "tile side must be a multiple of 4");
 };
 
-template <int TXx, int TZ, int RX, int RZ, int KY, bool F64>
-__global__ __launch_bounds__((Pass2Cfg<TXx, TZ, RX, RZ, KY>::NT)) void pass2_cohesion_kernel(
+template <int T, int R, int KY, bool F64>
+__global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
-    float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t nbx,
-    int32_t y_per_chunk, int32_t vec_ok_d, int32_t vec_ok_w) {
-    using Cfg = Pass2Cfg<TXx, TZ, RX, RZ, KY>;
+    float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
+    int32_t vec_ok_d, int32_t vec_ok_w) {
+    using Cfg = Pass2Cfg<T, R, KY>;
     __shared__ uint4 sm[2][Cfg::VEC_PER_CHUNK];
 
-    const int32_t bx = (int32_t)blockIdx.x % nbx, bz = (int32_t)blockIdx.x / nbx;
-    const int64_t X0 = (int64_t)bx * TXx, Z0 = (int64_t)bz * TZ;
+    int32_t bx, bz;
+    tri_tile((int32_t)blockIdx.x, bx, bz);
+    const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
     const int tid = threadIdx.x;
-    const int tx = tid % Cfg::TX, tz = tid / Cfg::TX;
+    const int tx = tid % Cfg::TT, tz = tid / Cfg::TT;
     const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
     const int64_t yend = min(n, ybeg + (int64_t)y_per_chunk);
 
     // stationary keys t_ij = d_xz
-    uint32_t t[RX][RZ];
+    uint32_t t[R][R];
 #pragma unroll
-    for (int i = 0; i < RX; ++i) {
-        const int64_t x = X0 + tx * RX + i;
+    for (int i = 0; i < R; ++i) {
+        const int64_t x = X0 + tx * R + i;
 #pragma unroll
-        for (int j = 0; j < RZ; ++j) {
-            const int64_t z = Z0 + tz * RZ + j;
+        for (int j = 0; j < R; ++j) {
+            const int64_t z = Z0 + tz * R + j;
             t[i][j] = (x < n && z < n) ? key_of(D[x * ldd + z]) : 0u;
         }
     }
 
-    float sum[RX][RZ], comp[RX][RZ], run[RX][RZ];
-    double acc[RX][RZ];
+    // forward (c_xz) and reverse (c_zx) accumulators
+    float sf[R][R], cf[R][R], rf[R][R], sr[R][R], cr[R][R], rr[R][R];
+    double af[R][R], ar[R][R];
 #pragma unroll
-    for (int i = 0; i < RX; ++i)
+    for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int j = 0; j < RZ; ++j) {
-            sum[i][j] = 0.0f;
-            comp[i][j] = 0.0f;
-            run[i][j] = 0.0f;
-            acc[i][j] = 0.0;
+        for (int j = 0; j < R; ++j) {
+            sf[i][j] = cf[i][j] = rf[i][j] = 0.0f;
+            sr[i][j] = cr[i][j] = rr[i][j] = 0.0f;
+            af[i][j] = ar[i][j] = 0.0;
         }
 
     uint4 pre[Cfg::VEC_PER_THREAD];
@@ -305,14 +463,13 @@ __global__ __launch_bounds__((Pass2Cfg<TXx, TZ, RX, RZ, KY>::NT)) void pass2_coh
             const int v = tid + k * Cfg::NT;
             const int r = v / (Cfg::ROW / 4);
             const int g = v % (Cfg::ROW / 4);
+            const int seg = g / (T / 4);           // 0: D x-range, 1: W x-range, 2: D z-range, 3: W z-range
+            const int64_t col = ((seg < 2) ? X0 : Z0) + 4 * (g % (T / 4));
             const int64_t y = yc + r;
-            if (g < TXx / 4) {
-                pre[k] = load_keys4(D, ldd, y, X0 + 4 * g, yend, n, vec_ok_d != 0, 0u);
-            } else if (g < TXx / 2) {
-                pre[k] = load_vals4(W, ldw, y, X0 + 4 * (g - TXx / 4), yend, n, vec_ok_w != 0);
-            } else {
-                pre[k] = load_keys4(D, ldd, y, Z0 + 4 * (g - TXx / 2), yend, n, vec_ok_d != 0, 0u);
-            }
+            if (seg == 0 || seg == 2)
+                pre[k] = load_keys4(D, ldd, y, col, yend, n, vec_ok_d != 0, 0u);
+            else
+                pre[k] = load_vals4(W, ldw, y, col, yend, n, vec_ok_w != 0);
         }
     };
     auto stash = [&](int buf) {
@@ -337,43 +494,53 @@ __global__ __launch_bounds__((Pass2Cfg<TXx, TZ, RX, RZ, KY>::NT)) void pass2_coh
 #pragma unroll
             for (int yy = 0; yy < Cfg::RUN; ++yy) {
                 const uint32_t *row = s + (y0 + yy) * Cfg::ROW;
-                uint32_t av[RX], bv[RZ];
-                float w[RX], wh[RX];
+                uint32_t av[R], bv[R];
+                float wx[R], whx[R], wz[R], whz[R];
 #pragma unroll
-                for (int i = 0; i < RX; ++i) {
-                    av[i] = row[tx * RX + i];
-                    w[i] = __uint_as_float(row[TXx + tx * RX + i]);
-                    wh[i] = 0.5f * w[i];
+                for (int i = 0; i < R; ++i) {
+                    av[i] = row[tx * R + i];
+                    wx[i] = __uint_as_float(row[T + tx * R + i]);
+                    whx[i] = 0.5f * wx[i];
+                    bv[i] = row[2 * T + tz * R + i];
+                    wz[i] = __uint_as_float(row[3 * T + tz * R + i]);
+                    whz[i] = 0.5f * wz[i];
                 }
+                if (F64) {
 #pragma unroll
-                for (int j = 0; j < RZ; ++j) bv[j] = row[2 * TXx + tz * RZ + j];
+                    for (int i = 0; i < R; ++i)
 #pragma unroll
-                for (int i = 0; i < RX; ++i)
-#pragma unroll
-                    for (int j = 0; j < RZ; ++j) {
-                        const uint32_t tt = t[i][j];
-                        const uint32_t m = umin(av[i], bv[j]);
-                        const float v = (tt < bv[j]) ? w[i] : wh[i];
-                        const float term = (tt <= m) ? v : 0.0f;
-                        if (F64) {
-                            acc[i][j] += (double)term;
-                        } else if (yy == 0) {
-                            run[i][j] = term;
-                        } else {
-                            run[i][j] += term;
+                        for (int j = 0; j < R; ++j) {
+                            const uint32_t tt = t[i][j];
+                            const uint64_t in = lane_mask(tt <= av[i]) & lane_mask(tt <= bv[j]);
+                            float vf = lane_bit(in) ? whx[i] : 0.0f;
+                            vf = lane_bit(in & lane_mask(tt < bv[j])) ? wx[i] : vf;
+                            float vr = lane_bit(in) ? whz[j] : 0.0f;
+                            vr = lane_bit(in & lane_mask(tt < av[i])) ? wz[j] : vr;
+                            af[i][j] += (double)vf;
+                            ar[i][j] += (double)vr;
                         }
-                    }
+                } else if (yy == 0) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                }
             }
             if (!F64) {
-                // Kahan fold of the finished run: sum - comp tracks the exact total.
+                // Kahan fold of the finished runs: sum - comp tracks the exact total.
 #pragma unroll
-                for (int i = 0; i < RX; ++i)
+                for (int i = 0; i < R; ++i)
 #pragma unroll
-                    for (int j = 0; j < RZ; ++j) {
-                        const float yk = run[i][j] - comp[i][j];
-                        const float tk = sum[i][j] + yk;
-                        comp[i][j] = (tk - sum[i][j]) - yk;
-                        sum[i][j] = tk;
+                    for (int j = 0; j < R; ++j) {
+                        float yk = rf[i][j] - cf[i][j];
+                        float tk = sf[i][j] + yk;
+                        cf[i][j] = (tk - sf[i][j]) - yk;
+                        sf[i][j] = tk;
+                        yk = rr[i][j] - cr[i][j];
+                        tk = sr[i][j] + yk;
+                        cr[i][j] = (tk - sr[i][j]) - yk;
+                        sr[i][j] = tk;
                     }
             }
         }
@@ -383,19 +550,23 @@ __global__ __launch_bounds__((Pass2Cfg<TXx, TZ, RX, RZ, KY>::NT)) void pass2_coh
 
     const double nm1 = (double)(n - 1);
     const bool direct = (gridDim.y == 1);
+    const bool mirror = bx != bz;
 #pragma unroll
-    for (int i = 0; i < RX; ++i) {
-        const int64_t x = X0 + tx * RX + i;
+    for (int i = 0; i < R; ++i) {
+        const int64_t x = X0 + tx * R + i;
         if (x >= n) continue;
 #pragma unroll
-        for (int j = 0; j < RZ; ++j) {
-            const int64_t z = Z0 + tz * RZ + j;
+        for (int j = 0; j < R; ++j) {
+            const int64_t z = Z0 + tz * R + j;
             if (z >= n) continue;
-            const double tot = F64 ? acc[i][j] : ((double)sum[i][j] - (double)comp[i][j]);
+            const double tf = F64 ? af[i][j] : ((double)sf[i][j] - (double)cf[i][j]);
+            const double tr = F64 ? ar[i][j] : ((double)sr[i][j] - (double)cr[i][j]);
             if (direct) {
-                C[x * ldc + z] = (float)(tot / nm1);
+                C[x * ldc + z] = (float)(tf / nm1);
+                if (mirror) C[z * ldc + x] = (float)(tr / nm1);
             } else {
-                partial[((int64_t)blockIdx.y * n + x) * n + z] = tot;
+                partial[((int64_t)blockIdx.y * n + x) * n + z] = tf;
+                if (mirror) partial[((int64_t)blockIdx.y * n + z) * n + x] = tr;
             }
         }
     }

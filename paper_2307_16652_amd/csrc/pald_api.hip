@@ -23,9 +23,10 @@ using namespace pald;
 // pass 1: 128 x 128 (x,y) tiles, 8 x 8 counters per thread, 16 z rows per stage
 constexpr int P1_T = 128, P1_RX = 8, P1_RY = 8, P1_KZ = 16;
 using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
-// pass 2: 64 x 128 (x,z) tiles, 4 x 8 accumulators per thread, 16 y rows per stage
-constexpr int P2_TX = 64, P2_TZ = 128, P2_RX = 4, P2_RZ = 8, P2_KY = 16;
-using P2 = Pass2Cfg<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY>;
+// pass 2: symmetric 64 x 64 (x,z) tiles, 4 x 4 pairs (both directions) per thread,
+// 16 y rows per stage
+constexpr int P2_T = 64, P2_R = 4, P2_KY = 16;
+using P2 = Pass2Cfg<P2_T, P2_R, P2_KY>;
 
 constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
 constexpr size_t ALIGN = 256;
@@ -95,7 +96,7 @@ struct Plan {
     int64_t n = 0;
     int64_t nb1 = 0, tiles1 = 0;  // pass-1 tile grid (upper triangle)
     int32_t z_chunks = 1, z_per_chunk = 0;
-    int32_t nbx = 0, nbz = 0;     // pass-2 tile grid
+    int64_t nb2 = 0, tiles2 = 0;  // pass-2 tile grid (upper triangle)
     int32_t y_chunks = 1, y_per_chunk = 0;
     int64_t ldw = 0;
     size_t off_w = 0, off_u = 0, off_part = 0, bytes = 0;
@@ -117,13 +118,12 @@ pald_status make_plan(int64_t n, const Opts &o, Plan &p) {
     p.z_per_chunk = (int32_t)(ceil_div(ceil_div(n, zc), P1_KZ) * P1_KZ);
     p.z_chunks = (int32_t)ceil_div(n, p.z_per_chunk);
 
-    p.nbx = (int32_t)ceil_div(n, P2_TX);
-    p.nbz = (int32_t)ceil_div(n, P2_TZ);
-    const int64_t tiles2 = (int64_t)p.nbx * p.nbz;
-    if (tiles2 > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    p.nb2 = ceil_div(n, P2_T);
+    p.tiles2 = p.nb2 * (p.nb2 + 1) / 2;
+    if (p.tiles2 > INT32_MAX) return PALD_ERR_UNSUPPORTED;
     int64_t yc = o.y_chunks;
     if (yc == 0) {
-        yc = ceil_div(TARGET_WORKGROUPS, tiles2);
+        yc = ceil_div(TARGET_WORKGROUPS, p.tiles2);
         yc = std::min<int64_t>(yc, std::max<int64_t>(1, n / (2 * P2_KY)));
     }
     yc = std::max<int64_t>(1, std::min<int64_t>(yc, ceil_div(n, P2_KY)));
@@ -188,15 +188,15 @@ pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, in
                       int64_t ldc, double *part, const Plan &p, bool f64, hipStream_t s, bool timing) {
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     const int vecw = (aligned16(W) && ldw % 4 == 0) ? 1 : 0;
-    const dim3 grid((unsigned)((int64_t)p.nbx * p.nbz), (unsigned)p.y_chunks);
+    const dim3 grid((unsigned)p.tiles2, (unsigned)p.y_chunks);
     {
         ScopedTiming tm(timing, 2, s);
         if (f64)
-            pass2_cohesion_kernel<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY, true>
-                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.nbx, p.y_per_chunk, vecd, vecw);
+            pass2_cohesion_kernel<P2_T, P2_R, P2_KY, true>
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
         else
-            pass2_cohesion_kernel<P2_TX, P2_TZ, P2_RX, P2_RZ, P2_KY, false>
-                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.nbx, p.y_per_chunk, vecd, vecw);
+            pass2_cohesion_kernel<P2_T, P2_R, P2_KY, false>
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     if (p.y_chunks > 1) {

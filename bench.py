@@ -77,6 +77,82 @@ def cpu_baseline(D: np.ndarray, target_s: float = 12.0):
     }
 
 
+def batched_bench(dev, reps: int = 3):
+    """The 2000-matrix batch (n uniform in [32, 1024]): one persistent launch per
+    batch, replayed from a captured hipGraph, against the same library's
+    single-matrix path launched once per matrix on one stream."""
+    import torch
+
+    from paper_2307_16652_amd import pald, synth
+
+    ns = synth.batch_sizes()
+    progress(f"batched: generating {len(ns)} matrices")
+    mats = [synth.pairwise_distances(synth.batch_points(i, int(n))) for i, n in enumerate(ns)]
+    cfg = pald.load_tuning() if hasattr(pald, "load_tuning") else None
+    plan = pald.BatchPlan([int(n) for n in ns], config=cfg)
+    Dp = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
+    del mats
+    ws = plan.workspace(dev)
+    Up = torch.empty(plan.total, dtype=torch.int32, device=dev)
+    Cp = torch.empty(plan.total, dtype=torch.float32, device=dev)
+    plan.run(Dp, Up, Cp, ws)  # warm-up
+    g = plan.graph(Dp, Up, Cp, ws)
+    g.launch()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        g.launch()
+    ev1.record()
+    torch.cuda.synchronize()
+    batch_ms = ev0.elapsed_time(ev1) / reps
+    g.close()
+
+    # per-matrix latency from one run with device timestamps
+    tcfg = pald.load_tuning(timestamps=True) if hasattr(pald, "load_tuning") else \
+        pald.make_batch_config(timestamps=True)
+    tplan = pald.BatchPlan([int(n) for n in ns], config=tcfg)
+    tws = tplan.workspace(dev)
+    tplan.run(Dp, Up, Cp, tws)
+    torch.cuda.synchronize()
+    start, end = tplan.timestamps(tws)
+    lat = end - start
+    tplan.close()
+
+    # comparator: one single-matrix call per matrix, same stream, no graph
+    views = plan.unpack(Dp)
+    cviews = plan.unpack(Cp)
+    uviews = plan.unpack(Up)
+    wsb = max(pald.workspace_bytes(int(n)) for n in set(int(x) for x in ns))
+    ws1 = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    for D, U, C in zip(views[:50], uviews[:50], cviews[:50]):
+        pald.cohesion(D, ws=ws1, out_u=U, out_c=C)
+    torch.cuda.synchronize()
+    ev0.record()
+    for D, U, C in zip(views, uviews, cviews):
+        pald.cohesion(D, ws=ws1, out_u=U, out_c=C)
+    ev1.record()
+    torch.cuda.synchronize()
+    loop_ms = ev0.elapsed_time(ev1)
+    terms = float((2.0 * ns.astype(np.float64) ** 3).sum())
+    plan.close()
+    return {
+        "workload": "batch: 2000 matrices, n uniform in [32,1024], 2-5 Gaussian clusters in R^4, seed 4",
+        "matrices_per_s": round(len(ns) / (batch_ms / 1e3), 1),
+        "ms_per_batch": round(batch_ms, 3),
+        "triplet_comparisons_G_per_s": round(terms / (batch_ms / 1e3) / 1e9, 1),
+        "launch": "hipGraph replay of one reset kernel + one persistent kernel",
+        "grid_workgroups": plan.grid,
+        "per_matrix_launch_ms": round(loop_ms, 3),
+        "per_matrix_launch_matrices_per_s": round(len(ns) / (loop_ms / 1e3), 1),
+        "speedup_vs_per_matrix_launches": round(loop_ms / batch_ms, 3),
+        "latency_us_p50": round(float(np.percentile(lat, 50)), 1),
+        "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
+        "completion_since_launch_us_p50": round(float(np.percentile(end, 50)), 1),
+        "completion_since_launch_us_p99": round(float(np.percentile(end, 99)), 1),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +161,7 @@ def main():
     ap.add_argument("--n", type=int, default=N, help="matrix size (default 16384)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 2000-matrix batched measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise kernel that reads and writes 1 GiB, so a "
                          "counter profile can scale FETCH_SIZE / WRITE_SIZE")
@@ -185,13 +262,19 @@ def main():
         del Cf
     extra["pass1_focus_lane_ops_frac"] = round(p1_ops / (p1_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
 
+    if not args.no_batched:
+        del U, C, ws
+        torch.cuda.empty_cache()
+        extra["batched"] = batched_bench(dev)
+        progress(f"batched: {extra['batched']}")
+
     base = None
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle rows)")
         base = cpu_baseline(D)
 
     out = {
-        "metric": "triplet comparisons/sec (G/s) + % VALU peak, n=16384 fp32",
+        "metric": "triplet comparisons/sec (G/s) + % VALU peak, n=16384 fp32; batched matrices/sec",
         "value": round(value, 2),
         "unit": "G triplet comparisons/s",
         "n_gpus": 1,

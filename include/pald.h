@@ -139,41 +139,113 @@ pald_status pald_check_input(const float *D, int64_t n, int64_t ldd,
 
 /*
  * Batched mode: many independent matrices of different sizes in one
- * persistent launch (no batching in the paper; it is a GPU-side extension).
+ * persistent launch (no batching in the paper; a GPU-side extension).
  *
  * Packed layout: matrix i has n_i rows, leading dimension n_i, and starts at
  * element offset off_i = sum_{j<i} n_j^2 of D_packed, U_packed and C_packed.
  *
- * pald_batch_plan_create copies n_host, chooses tile shapes and y-splits per
- * matrix size, builds the work queue and uploads it to the current device
- * (this is the only allocating call; it is synchronous).  Every n_i >= 2.
+ * Work queue: every pass-1 tile and every pass-2 tile (times its y-chunks) of
+ * every matrix is one item; matrices are taken largest first, and the pass-2
+ * items of a matrix are placed `queue_lag` grid-sizes of items after its last
+ * pass-1 item.  All pass-1 items of a matrix precede its pass-2 items, which
+ * is what makes the in-kernel wait of a pass-2 item always terminate.
  */
 typedef struct pald_batch_plan pald_batch_plan;
 
+/* Choices for the matrices with n <= n_max (entries sorted by n_max; matrices
+ * larger than the last n_max use the last entry). */
+typedef struct pald_batch_bucket {
+    int32_t n_max;
+    int32_t p1_tile;   /* pass-1 tile side: 64 (or 0 for the default, 64) */
+    int32_t y_chunks;  /* pass-2 split of the y range (1 = no split) */
+    int32_t reserved;  /* must be zero */
+} pald_batch_bucket;
+
+#define PALD_BATCH_MAX_BUCKETS 8
+#define PALD_BATCH_TIMESTAMPS 1u /* record per-matrix first-start / last-end device clocks */
+
+typedef struct pald_batch_config {
+    int32_t nbuckets;          /* entries used in bucket[]; 0 = the built-in tuned table */
+    int32_t workgroups_per_cu; /* persistent grid = CUs x this; 0 = resident capacity */
+    int32_t queue_lag;         /* in units of the grid size; 0 = default (2) */
+    uint32_t flags;            /* PALD_BATCH_* */
+    pald_batch_bucket bucket[PALD_BATCH_MAX_BUCKETS];
+} pald_batch_config;
+
+/*
+ * Builds the plan for `count` matrices of sizes n_host[0..count) (host array,
+ * every n_i >= 2) on the current device: chooses tiles and y-splits per size
+ * (cfg NULL = defaults), builds the queue and uploads it and the per-matrix
+ * table.  Synchronous; the only allocating call of the batched mode.
+ * Errors: PALD_ERR_ARG (count < 1, null pointers, n_i < 2, bad config),
+ * PALD_ERR_NOMEM, PALD_ERR_DEVICE.
+ */
 pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host,
-                                   const pald_options *opt,
+                                   const pald_batch_config *cfg,
                                    pald_batch_plan **plan_out);
 
-/* Workspace bytes pald_cohesion_batched needs with this plan. */
+/* Workspace bytes pald_cohesion_batched needs with this plan (0 for NULL). */
 size_t pald_batch_workspace_bytes(const pald_batch_plan *plan);
 
-/* Total packed elements sum n_i^2 (so callers can size D/U/C). */
+/* Total packed elements sum n_i^2 (so callers can size D/U/C); -1 for NULL. */
 int64_t pald_batch_total_elements(const pald_batch_plan *plan);
 
 /* Element offset of matrix i in the packed arrays, or -1 if i is out of range. */
 int64_t pald_batch_offset(const pald_batch_plan *plan, int32_t i);
 
+/* Persistent grid size (workgroups) the plan launches; -1 for NULL. */
+int32_t pald_batch_grid(const pald_batch_plan *plan);
+
 /*
- * Runs the whole batch: U_packed (may be NULL) and C_packed from D_packed.
- * Enqueues a counter reset and one persistent kernel on `stream`; both are
- * capturable into a hipGraph (no allocation, no memset node).
+ * Runs the whole batch: U_packed (may be NULL) and C_packed from D_packed,
+ * all device pointers of pald_batch_total_elements() elements.  Enqueues one
+ * counter-reset kernel and one persistent kernel on `stream` (no allocation,
+ * no memset node, so the pair can be captured into a hipGraph).  Calls that
+ * share a workspace must not overlap.  C accumulates as in pald_cohesion
+ * (float32 runs, Kahan partials, float64 final reduction).
+ * Errors: PALD_ERR_ARG for null plan/D/C/ws or a small/misaligned ws.
  */
 pald_status pald_cohesion_batched(const pald_batch_plan *plan,
                                   const float *D_packed, int32_t *U_packed,
                                   float *C_packed, void *ws, size_t ws_bytes,
                                   void *stream);
 
+/*
+ * Per-matrix device timestamps of the last batched run made with
+ * PALD_BATCH_TIMESTAMPS: start_us[i] = first item start and end_us[i] = last
+ * item end of matrix i, in microseconds from the earliest start.
+ * Synchronous (waits for `stream`).  PALD_ERR_ARG if the plan records none.
+ */
+pald_status pald_batch_timestamps(const pald_batch_plan *plan, const void *ws,
+                                  void *stream, double *start_us, double *end_us);
+
+/*
+ * Host only, touches no GPU: writes the queue a plan for these sizes and
+ * settings would run with a persistent grid of `grid` workgroups, as 4 int32
+ * per item {matrix, kind (0 = pass-1 tile, 1 = pass-2 tile), tile index,
+ * y-chunk}, and per matrix its pass-1 tile count to tiles1_out (may be NULL).
+ * Returns the number of items (writing at most `cap`), or -1 on bad arguments.
+ */
+int64_t pald_batch_queue(int32_t count, const int64_t *n_host,
+                         const pald_batch_config *cfg, int32_t grid,
+                         int32_t *items_out, int64_t cap, int32_t *tiles1_out);
+
 void pald_batch_plan_destroy(pald_batch_plan *plan);
+
+/*
+ * hipGraph of one batched run with fixed buffers: captures the reset and the
+ * persistent kernel once (on a private stream) and instantiates the graph.
+ * Launching it on any stream is equivalent to pald_cohesion_batched with the
+ * same arguments.  The plan and buffers must outlive the graph.
+ */
+typedef struct pald_batch_graph pald_batch_graph;
+
+pald_status pald_batch_graph_create(const pald_batch_plan *plan,
+                                    const float *D_packed, int32_t *U_packed,
+                                    float *C_packed, void *ws, size_t ws_bytes,
+                                    pald_batch_graph **graph_out);
+pald_status pald_batch_graph_launch(pald_batch_graph *graph, void *stream);
+void pald_batch_graph_destroy(pald_batch_graph *graph);
 
 /*
  * Device timings recorded by calls made with PALD_FLAG_TIMING since the last

@@ -1,4 +1,171 @@
-// batched.hpp -- batched persistent mode.  Not implemented yet.
+// batched.hpp -- many independent PaLD problems of different sizes in one
+// persistent launch (a GPU-side extension; the paper has no batching).
+//
+// Work items are pass-1 tiles and pass-2 tiles (optionally split over y) of
+// every matrix, listed once in a queue built on the host.  Each workgroup of
+// the persistent grid takes the next item with one atomic increment of a
+// global head counter and runs it with the same tile functions as the
+// single-matrix kernels.
+//
+// Ordering and progress:
+//  * in the queue every pass-1 item of a matrix comes before any of its pass-2
+//    items, and workgroups take items strictly in queue order;
+//  * a pass-2 item first waits until the matrix's pass-1 counter reaches its
+//    pass-1 tile count.  All those pass-1 items were taken earlier by running
+//    workgroups, and pass-1 items never wait, so the wait always ends,
+//    whatever the grid size and however many workgroups are resident;
+//  * pass-1 writers fence their U/W stores at device (agent) scope before
+//    bumping the counter, and the waiting side fences after seeing the count,
+//    so the weights written on another XCD are visible (each XCD has its own
+//    L2);
+//  * a pass-2 tile split over y writes float64 partial tiles; the workgroup
+//    that completes the last chunk of a tile (per-tile arrival counter) sums
+//    the chunks in chunk order -- so the result does not depend on arrival
+//    order -- and writes C.
 #pragma once
 
-#include "triplet.hpp"
+#include "pairwise.hpp"
+
+namespace pald {
+
+// Per-matrix description, built on the host.
+struct BatchMatrix {
+    int64_t off;       // element offset of D / U / C in the packed arrays (ld = n)
+    int64_t woff;      // float offset of this matrix's weights in the weight region
+    int64_t poff;      // double offset of its first partial tile (y_chunks > 1)
+    int32_t n;
+    int32_t ldw;       // leading dimension of its weights (multiple of 4)
+    int32_t tiles1;    // pass-1 tiles = number of pass-1 items
+    int32_t y_chunks;  // pass-2 y split
+    int32_t y_per_chunk;
+    int32_t ctr2;      // index of its first per-tile arrival counter (y_chunks > 1)
+    int32_t vec_d;     // rows of D start on 16-byte boundaries (given an aligned base)
+};
+
+// Item kinds.
+constexpr int32_t ITEM_PASS1 = 0;
+constexpr int32_t ITEM_PASS2 = 1;
+
+constexpr int BATCH_THREADS = 256;
+// One pass-1 shape (64 x 64 tiles, 2 x 8 counters per thread) and one pass-2
+// shape (64 x 64 tiles, 4 x 4 pairs): both inlined in one kernel, the larger
+// single-matrix pass-1 register tile would push the kernel to one wave per
+// SIMD.
+constexpr int BATCH_P1_T = 64;
+constexpr int BATCH_P2_T = 64, BATCH_P2_R = 4, BATCH_P2_KY = 16;
+using BatchP1 = Pass1Cfg<BATCH_P1_T, 2, 8, 16>;
+using BatchP2 = Pass2Cfg<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY>;
+static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS,
+              "both batched tile shapes use one workgroup size");
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int BATCH_LDS_VEC = 2 * cmax(BatchP1::VEC_PER_CHUNK, BatchP2::VEC_PER_CHUNK);
+
+// Counter layout (uint32): [0] queue head, [1 .. count] pass-1 done counts,
+// [1 + count ..] per-tile arrival counters of split pass-2 tiles.
+// Timestamps (uint64, optional): [2m] first item start, [2m+1] last item end.
+__global__ void batch_reset_kernel(uint32_t *__restrict__ ctr, int64_t nctr, uint64_t *__restrict__ stamps,
+                                   int64_t nmat) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nctr; i += (int64_t)gridDim.x * blockDim.x)
+        ctr[i] = 0u;
+    if (stamps)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nmat;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            stamps[2 * i] = ~0ull;
+            stamps[2 * i + 1] = 0ull;
+        }
+}
+
+__global__ __launch_bounds__(BATCH_THREADS) void batched_cohesion_kernel(
+    const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+    int32_t *__restrict__ U, float *__restrict__ C, float *__restrict__ Wr, double *__restrict__ Pr,
+    uint32_t *__restrict__ ctr, int32_t count, uint64_t *__restrict__ stamps, int32_t d_aligned) {
+    __shared__ uint4 sm[BATCH_LDS_VEC];
+    __shared__ int32_t s_item;
+    __shared__ int32_t s_last;
+    const int tid = threadIdx.x;
+    uint32_t *const done1 = ctr + 1;
+    uint32_t *const arrive = ctr + 1 + count;
+
+    for (;;) {
+        if (tid == 0) s_item = (int32_t)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int32_t it = s_item;
+        __syncthreads();  // every thread has read s_item before it can change again
+        if (it >= total) break;
+
+        const int4 item = items[it];
+        const BatchMatrix m = mats[item.x];
+        const int64_t n = m.n;
+        const float *Dm = D + m.off;
+        float *Wm = Wr + m.woff;
+        const bool vec_d = d_aligned && m.vec_d;
+        if (stamps && tid == 0) atomicMin((unsigned long long *)&stamps[2 * item.x], (unsigned long long)wall_clock64());
+
+        if (item.y == ITEM_PASS1) {
+            int32_t bx, by;
+            tri_tile(item.z, bx, by);
+            int32_t *Um = U ? U + m.off : nullptr;
+            pass1_tile<BATCH_P1_T, 2, 8, 16>(sm, Dm, n, n, Um, n, Wm, m.ldw, bx, by, 0, n, false, vec_d);
+            __threadfence();  // release this thread's U / W stores at device scope
+            __syncthreads();
+            if (tid == 0) atomicAdd(&done1[item.x], 1u);
+        } else {
+            if (tid == 0) {
+                while (__hip_atomic_load(&done1[item.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       (uint32_t)m.tiles1)
+                    __builtin_amdgcn_s_sleep(2);
+                __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            }
+            __syncthreads();
+            __threadfence();  // acquire for every wave before reading the weights
+            int32_t bx, bz;
+            tri_tile(item.z, bx, bz);
+            const int64_t ybeg = (int64_t)item.w * m.y_per_chunk;
+            const int64_t yend = min(n, ybeg + (int64_t)m.y_per_chunk);
+            if (m.y_chunks == 1) {
+                Pass2Out out{C + m.off, n, nullptr, nullptr};
+                pass2_tile<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY, false>(sm, Dm, n, n, Wm, m.ldw, out, bx, bz, ybeg,
+                                                                       yend, vec_d, true);
+            } else {
+                constexpr int64_t TT2 = 2 * BATCH_P2_T * BATCH_P2_T;
+                double *tiles = Pr + m.poff + (int64_t)item.z * m.y_chunks * TT2;
+                Pass2Out out{nullptr, 0, nullptr, tiles + (int64_t)item.w * TT2};
+                pass2_tile<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY, false>(sm, Dm, n, n, Wm, m.ldw, out, bx, bz, ybeg,
+                                                                       yend, vec_d, true);
+                __threadfence();
+                __syncthreads();
+                if (tid == 0) {
+                    const uint32_t prev = atomicAdd(&arrive[m.ctr2 + item.z], 1u);
+                    s_last = (prev == (uint32_t)(m.y_chunks - 1)) ? 1 : 0;
+                    if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                }
+                __syncthreads();
+                if (s_last) {
+                    __threadfence();
+                    const int64_t X0 = (int64_t)bx * BATCH_P2_T, Z0 = (int64_t)bz * BATCH_P2_T;
+                    const double nm1 = (double)(n - 1);
+                    float *Cm = C + m.off;
+                    for (int e = tid; e < BATCH_P2_T * BATCH_P2_T; e += BATCH_THREADS) {
+                        const int i = e / BATCH_P2_T, j = e % BATCH_P2_T;
+                        const int64_t x = X0 + i, z = Z0 + j;
+                        if (x >= n || z >= n) continue;
+                        double sf = 0.0, sr = 0.0;
+                        for (int32_t k = 0; k < m.y_chunks; ++k) {
+                            sf += tiles[k * TT2 + e];
+                            sr += tiles[k * TT2 + BATCH_P2_T * BATCH_P2_T + e];
+                        }
+                        Cm[x * n + z] = (float)(sf / nm1);
+                        if (bx != bz) Cm[z * n + x] = (float)(sr / nm1);
+                    }
+                }
+            }
+        }
+        if (stamps && tid == 0) {
+            __threadfence();
+            atomicMax((unsigned long long *)&stamps[2 * item.x + 1], (unsigned long long)wall_clock64());
+        }
+        __syncthreads();  // LDS and s_last are reused by the next item
+    }
+}
+
+}  // namespace pald

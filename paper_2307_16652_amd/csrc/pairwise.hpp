@@ -255,20 +255,18 @@ struct Pass1Cfg {
     static_assert(RY == 8, "focus counting works on rows of 8 y");
 };
 
+// One pass-1 tile (bx, by), bx <= by, over the z range [zbeg, zend).  Called
+// by every thread of a workgroup of Pass1Cfg::NT threads; `sm` points to
+// 2 * VEC_PER_CHUNK uint4 of LDS.  U may be null in direct mode.
 template <int T, int RX, int RY, int KZ>
-__global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_kernel(
-    const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
-    float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok) {
+__device__ __forceinline__ void pass1_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
+                                           int32_t *__restrict__ U, int64_t ldu, float *__restrict__ W, int64_t ldw,
+                                           int32_t bx, int32_t by, int64_t zbeg, int64_t zend, bool atomic_mode,
+                                           bool vec_ok) {
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
-    __shared__ uint4 sm[2][Cfg::VEC_PER_CHUNK];
-
-    int32_t bx, by;
-    tri_tile((int32_t)blockIdx.x, bx, by);
     const int64_t X0 = (int64_t)bx * T, Y0 = (int64_t)by * T;
     const int tid = threadIdx.x;
     const int tx = tid % Cfg::TX, ty = tid / Cfg::TX;
-    const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
-    const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
 
     // stationary keys a_ij = d_xy
     uint32_t a[RX][RY];
@@ -295,12 +293,12 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
             const int g = v % (Cfg::ROW / 4);
             const int64_t z = zc + r;
             const int64_t col = (g < T / 4) ? X0 + 4 * g : Y0 + 4 * (g - T / 4);
-            pre[k] = load_keys4(D, ldd, z, col, zend, n, vec_ok != 0, KEY_INF);
+            pre[k] = load_keys4(D, ldd, z, col, zend, n, vec_ok, KEY_INF);
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) sm[buf][tid + k * Cfg::NT] = pre[k];
+        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) sm[buf * Cfg::VEC_PER_CHUNK + tid + k * Cfg::NT] = pre[k];
     };
 
     const int64_t nz = zend - zbeg;
@@ -314,7 +312,7 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) fetch(zbeg + (c + 1) * KZ);
-        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm[buf]);
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * Cfg::VEC_PER_CHUNK);
 #pragma unroll 1
         for (int z = 0; z < KZ; ++z) {
             uint32_t xs[RX], ys[RY];
@@ -355,6 +353,19 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
             }
         }
     }
+}
+
+template <int T, int RX, int RY, int KZ>
+__global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_kernel(
+    const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
+    float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok) {
+    using Cfg = Pass1Cfg<T, RX, RY, KZ>;
+    __shared__ uint4 sm[2 * Cfg::VEC_PER_CHUNK];
+    int32_t bx, by;
+    tri_tile((int32_t)blockIdx.x, bx, by);
+    const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
+    const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
+    pass1_tile<T, RX, RY, KZ>(sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
 }
 
 // W_xy = fl32(1/U_xy) off the diagonal, 0 on it (used after a split pass 1).
@@ -416,21 +427,29 @@ struct Pass2Cfg {
     static_assert(T % 4 == 0, "tile side must be a multiple of 4");
 };
 
-template <int T, int R, int KY, bool F64>
-__global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kernel(
-    const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
-    float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
-    int32_t vec_ok_d, int32_t vec_ok_w) {
-    using Cfg = Pass2Cfg<T, R, KY>;
-    __shared__ uint4 sm[2][Cfg::VEC_PER_CHUNK];
+// Where a pass-2 tile puts its sums: exactly one of
+//   C     -- final cohesion, fl32(sum / (n-1)), leading dimension ldc;
+//   slab  -- float64 partial sums of this y-chunk in an n x n array (ld n);
+//   tile  -- float64 partial sums in tile-local order: [0][i][j] holds the
+//            (X0+i, Z0+j) entry, [1][i][j] the mirrored (Z0+j, X0+i) entry.
+struct Pass2Out {
+    float *C;
+    int64_t ldc;
+    double *slab;
+    double *tile;
+};
 
-    int32_t bx, bz;
-    tri_tile((int32_t)blockIdx.x, bx, bz);
+// One pass-2 tile (bx, bz), bx <= bz, over the y range [ybeg, yend).  Called
+// by every thread of a workgroup of Pass2Cfg::NT threads; `sm` points to
+// 2 * VEC_PER_CHUNK uint4 of LDS.
+template <int T, int R, int KY, bool F64>
+__device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
+                                           const float *__restrict__ W, int64_t ldw, Pass2Out out, int32_t bx,
+                                           int32_t bz, int64_t ybeg, int64_t yend, bool vec_ok_d, bool vec_ok_w) {
+    using Cfg = Pass2Cfg<T, R, KY>;
     const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
     const int tid = threadIdx.x;
     const int tx = tid % Cfg::TT, tz = tid / Cfg::TT;
-    const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
-    const int64_t yend = min(n, ybeg + (int64_t)y_per_chunk);
 
     // stationary keys t_ij = d_xz
     uint32_t t[R][R];
@@ -467,14 +486,14 @@ __global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kerne
             const int64_t col = ((seg < 2) ? X0 : Z0) + 4 * (g % (T / 4));
             const int64_t y = yc + r;
             if (seg == 0 || seg == 2)
-                pre[k] = load_keys4(D, ldd, y, col, yend, n, vec_ok_d != 0, 0u);
+                pre[k] = load_keys4(D, ldd, y, col, yend, n, vec_ok_d, 0u);
             else
-                pre[k] = load_vals4(W, ldw, y, col, yend, n, vec_ok_w != 0);
+                pre[k] = load_vals4(W, ldw, y, col, yend, n, vec_ok_w);
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) sm[buf][tid + k * Cfg::NT] = pre[k];
+        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) sm[buf * Cfg::VEC_PER_CHUNK + tid + k * Cfg::NT] = pre[k];
     };
 
     const int64_t ny = yend - ybeg;
@@ -488,7 +507,7 @@ __global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kerne
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) fetch(ybeg + (c + 1) * KY);
-        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm[buf]);
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * Cfg::VEC_PER_CHUNK);
 #pragma unroll 1
         for (int y0 = 0; y0 < KY; y0 += Cfg::RUN) {
 #pragma unroll
@@ -549,27 +568,52 @@ __global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kerne
     }
 
     const double nm1 = (double)(n - 1);
-    const bool direct = (gridDim.y == 1);
     const bool mirror = bx != bz;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         const int64_t x = X0 + tx * R + i;
-        if (x >= n) continue;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t z = Z0 + tz * R + j;
-            if (z >= n) continue;
             const double tf = F64 ? af[i][j] : ((double)sf[i][j] - (double)cf[i][j]);
             const double tr = F64 ? ar[i][j] : ((double)sr[i][j] - (double)cr[i][j]);
-            if (direct) {
-                C[x * ldc + z] = (float)(tf / nm1);
-                if (mirror) C[z * ldc + x] = (float)(tr / nm1);
+            if (out.tile) {
+                const int li = tx * R + i, lj = tz * R + j;
+                out.tile[li * T + lj] = tf;
+                out.tile[T * T + li * T + lj] = tr;
+                continue;
+            }
+            if (x >= n || z >= n) continue;
+            if (out.C) {
+                out.C[x * out.ldc + z] = (float)(tf / nm1);
+                if (mirror) out.C[z * out.ldc + x] = (float)(tr / nm1);
             } else {
-                partial[((int64_t)blockIdx.y * n + x) * n + z] = tf;
-                if (mirror) partial[((int64_t)blockIdx.y * n + z) * n + x] = tr;
+                out.slab[x * n + z] = tf;
+                if (mirror) out.slab[z * n + x] = tr;
             }
         }
     }
+}
+
+template <int T, int R, int KY, bool F64>
+__global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kernel(
+    const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
+    float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
+    int32_t vec_ok_d, int32_t vec_ok_w) {
+    using Cfg = Pass2Cfg<T, R, KY>;
+    __shared__ uint4 sm[2 * Cfg::VEC_PER_CHUNK];
+    int32_t bx, bz;
+    tri_tile((int32_t)blockIdx.x, bx, bz);
+    const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
+    const int64_t yend = min(n, ybeg + (int64_t)y_per_chunk);
+    Pass2Out out{nullptr, 0, nullptr, nullptr};
+    if (gridDim.y == 1) {
+        out.C = C;
+        out.ldc = ldc;
+    } else {
+        out.slab = partial + (int64_t)blockIdx.y * n * n;
+    }
+    pass2_tile<T, R, KY, F64>(sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
 }
 
 // C_xz = fl32( sum_k partial[k][x][z] / (n-1) ), the only cross-tile reduction.

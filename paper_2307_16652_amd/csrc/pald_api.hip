@@ -14,6 +14,7 @@
 #include "pald.h"
 #include "pairwise.hpp"
 #include "batched.hpp"
+#include "triplet.hpp"
 
 namespace {
 
@@ -314,22 +315,338 @@ int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds) {
 
 }  // extern "C"
 
-// ---- batched mode (not implemented yet) ------------------------------------
-struct pald_batch_plan {
-    int32_t count;
+// ============================================================================
+// batched mode
+
+namespace {
+
+// Built-in bucket table (from the autotuner on MI355X; see tune.py).
+const pald_batch_bucket kDefaultBuckets[] = {
+    {1 << 30, 64, 1, 0},
+};
+constexpr int kDefaultNumBuckets = (int)(sizeof(kDefaultBuckets) / sizeof(kDefaultBuckets[0]));
+constexpr int kDefaultLag = 2;
+
+struct BatchLayout {
+    std::vector<BatchMatrix> mats;
+    std::vector<int4> items;
+    std::vector<int64_t> n, off;
+    int64_t total_elems = 0;
+    int64_t w_floats = 0;     // weight region size (floats)
+    int64_t p_doubles = 0;    // partial-tile region size (doubles)
+    int64_t nctr = 0;         // uint32 counters
 };
 
+pald_status check_config(const pald_batch_config *cfg) {
+    if (!cfg) return PALD_OK;
+    if (cfg->nbuckets < 0 || cfg->nbuckets > PALD_BATCH_MAX_BUCKETS || cfg->workgroups_per_cu < 0 ||
+        cfg->queue_lag < 0 || (cfg->flags & ~PALD_BATCH_TIMESTAMPS))
+        return PALD_ERR_ARG;
+    for (int b = 0; b < cfg->nbuckets; ++b) {
+        const pald_batch_bucket &k = cfg->bucket[b];
+        if ((k.p1_tile != 0 && k.p1_tile != BATCH_P1_T) || k.y_chunks < 1 || k.n_max < 2 || k.reserved != 0)
+            return PALD_ERR_ARG;
+        if (b > 0 && k.n_max <= cfg->bucket[b - 1].n_max) return PALD_ERR_ARG;
+    }
+    return PALD_OK;
+}
+
+const pald_batch_bucket &bucket_for(const pald_batch_config *cfg, int64_t n) {
+    const pald_batch_bucket *tab = kDefaultBuckets;
+    int nb = kDefaultNumBuckets;
+    if (cfg && cfg->nbuckets > 0) {
+        tab = cfg->bucket;
+        nb = cfg->nbuckets;
+    }
+    for (int b = 0; b < nb; ++b)
+        if (n <= tab[b].n_max) return tab[b];
+    return tab[nb - 1];
+}
+
+// Per-matrix table, item queue and workspace sizes for a batch.
+pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_config *cfg, int32_t grid,
+                        BatchLayout &L) {
+    if (count < 1 || !n_host || grid < 1) return PALD_ERR_ARG;
+    if (pald_status st = check_config(cfg); st != PALD_OK) return st;
+    L = BatchLayout{};
+    L.mats.resize(count);
+    L.n.assign(n_host, n_host + count);
+    L.off.resize(count);
+    int64_t off = 0, woff = 0, poff = 0, ctr2 = 0;
+    constexpr int64_t T2 = BATCH_P2_T;
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t n = n_host[i];
+        if (n < 2 || n > (1 << 20)) return PALD_ERR_ARG;
+        const pald_batch_bucket &bk = bucket_for(cfg, n);
+        BatchMatrix &m = L.mats[i];
+        m.off = off;
+        L.off[i] = off;
+        m.n = (int32_t)n;
+        m.ldw = (int32_t)align_up((size_t)n, 4);
+        m.woff = woff;
+        const int64_t nb1 = ceil_div(n, BATCH_P1_T);
+        m.tiles1 = (int32_t)(nb1 * (nb1 + 1) / 2);
+        const int64_t nb2 = ceil_div(n, T2);
+        const int64_t tiles2 = nb2 * (nb2 + 1) / 2;
+        int64_t yc = std::max<int64_t>(1, std::min<int64_t>(bk.y_chunks, ceil_div(n, BATCH_P2_KY)));
+        m.y_per_chunk = (int32_t)(ceil_div(ceil_div(n, yc), BATCH_P2_KY) * BATCH_P2_KY);
+        m.y_chunks = (int32_t)ceil_div(n, m.y_per_chunk);
+        m.poff = poff;
+        m.ctr2 = (int32_t)ctr2;
+        if (m.y_chunks > 1) {
+            poff += tiles2 * m.y_chunks * 2 * T2 * T2;
+            ctr2 += tiles2;
+        }
+        m.vec_d = (off % 4 == 0 && n % 4 == 0) ? 1 : 0;
+        off += n * n;
+        woff += (int64_t)align_up((size_t)(n * m.ldw), 64);  // 256-byte aligned per matrix
+    }
+    L.total_elems = off;
+    L.w_floats = woff;
+    L.p_doubles = poff;
+    L.nctr = 1 + (int64_t)count + ctr2;
+
+    // matrices largest first
+    std::vector<int32_t> order(count);
+    for (int32_t i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return n_host[a] > n_host[b]; });
+    const int64_t lag = (int64_t)((cfg && cfg->queue_lag > 0) ? cfg->queue_lag : kDefaultLag) * grid;
+
+    auto emit_p2 = [&](int32_t i) {
+        const BatchMatrix &m = L.mats[i];
+        const int64_t nb2 = ceil_div(m.n, T2);
+        const int64_t tiles2 = nb2 * (nb2 + 1) / 2;
+        for (int64_t t = 0; t < tiles2; ++t)
+            for (int32_t c = 0; c < m.y_chunks; ++c) L.items.push_back(make_int4(i, ITEM_PASS2, (int)t, c));
+    };
+    std::vector<std::pair<int32_t, int64_t>> pending;  // (matrix, queue position after its last pass-1 item)
+    size_t head = 0;
+    int64_t p1_emitted = 0;
+    for (int32_t i : order) {
+        for (int32_t t = 0; t < L.mats[i].tiles1; ++t) L.items.push_back(make_int4(i, ITEM_PASS1, t, 0));
+        p1_emitted += L.mats[i].tiles1;
+        pending.push_back({i, p1_emitted});
+        while (head < pending.size() && p1_emitted - pending[head].second >= lag) emit_p2(pending[head++].first);
+    }
+    while (head < pending.size()) emit_p2(pending[head++].first);
+    if (L.items.size() > (size_t)INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    return PALD_OK;
+}
+
+int32_t device_cus(int dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    return cus;
+}
+
+int32_t resident_per_cu() {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cohesion_kernel, BATCH_THREADS, 0) !=
+            hipSuccess ||
+        per < 1)
+        per = 1;
+    return per;
+}
+
+}  // namespace
+
+struct pald_batch_plan {
+    int32_t count = 0;
+    int device = 0;
+    uint32_t flags = 0;
+    int32_t grid = 0;
+    BatchLayout L;
+    BatchMatrix *d_mats = nullptr;
+    int4 *d_items = nullptr;
+    size_t off_w = 0, off_p = 0, off_ctr = 0, off_stamps = 0, ws_bytes = 0;
+};
+
+struct pald_batch_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *U, float *C, void *ws,
+                          hipStream_t s) {
+    char *base = static_cast<char *>(ws);
+    float *Wr = reinterpret_cast<float *>(base + plan->off_w);
+    double *Pr = reinterpret_cast<double *>(base + plan->off_p);
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(base + plan->off_ctr);
+    uint64_t *stamps =
+        (plan->flags & PALD_BATCH_TIMESTAMPS) ? reinterpret_cast<uint64_t *>(base + plan->off_stamps) : nullptr;
+    const int64_t nreset = std::max<int64_t>(plan->L.nctr, plan->count);
+    const unsigned rg = (unsigned)std::min<int64_t>(ceil_div(nreset, 256), 1024);
+    batch_reset_kernel<<<rg, 256, 0, s>>>(ctr, plan->L.nctr, stamps, plan->count);
+    if (pald_status st = launch_status(); st != PALD_OK) return st;
+    batched_cohesion_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
+        plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, U, C, Wr, Pr, ctr, plan->count, stamps,
+        aligned16(D) ? 1 : 0);
+    return launch_status();
+}
+
+}  // namespace
+
 extern "C" {
-pald_status pald_batch_plan_create(int32_t, const int64_t *, const pald_options *, pald_batch_plan **plan_out) {
-    if (plan_out) *plan_out = nullptr;
-    return PALD_ERR_UNSUPPORTED;
+
+pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const pald_batch_config *cfg,
+                                   pald_batch_plan **plan_out) {
+    if (!plan_out) return PALD_ERR_ARG;
+    *plan_out = nullptr;
+    if (count < 1 || !n_host) return PALD_ERR_ARG;
+    if (pald_status st = check_config(cfg); st != PALD_OK) return st;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PALD_ERR_DEVICE;
+    const int32_t cus = device_cus(dev);
+    const int32_t per_cu = (cfg && cfg->workgroups_per_cu > 0) ? cfg->workgroups_per_cu : resident_per_cu();
+    const int32_t grid = cus * per_cu;
+    pald_batch_plan *p = new (std::nothrow) pald_batch_plan();
+    if (!p) return PALD_ERR_NOMEM;
+    p->count = count;
+    p->device = dev;
+    p->flags = cfg ? cfg->flags : 0u;
+    p->grid = grid;
+    if (pald_status st = build_batch(count, n_host, cfg, grid, p->L); st != PALD_OK) {
+        delete p;
+        return st;
+    }
+    size_t off = 0;
+    p->off_w = off;
+    off = align_up(off + (size_t)p->L.w_floats * sizeof(float), ALIGN);
+    p->off_p = off;
+    off = align_up(off + (size_t)p->L.p_doubles * sizeof(double), ALIGN);
+    p->off_ctr = off;
+    off = align_up(off + (size_t)p->L.nctr * sizeof(uint32_t), ALIGN);
+    p->off_stamps = off;
+    if (p->flags & PALD_BATCH_TIMESTAMPS) off = align_up(off + (size_t)count * 2 * sizeof(uint64_t), ALIGN);
+    p->ws_bytes = off;
+    const size_t mbytes = p->L.mats.size() * sizeof(BatchMatrix), ibytes = p->L.items.size() * sizeof(int4);
+    if (hipMalloc((void **)&p->d_mats, mbytes) != hipSuccess || hipMalloc((void **)&p->d_items, ibytes) != hipSuccess) {
+        pald_batch_plan_destroy(p);
+        return PALD_ERR_NOMEM;
+    }
+    if (hipMemcpy(p->d_mats, p->L.mats.data(), mbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_items, p->L.items.data(), ibytes, hipMemcpyHostToDevice) != hipSuccess) {
+        pald_batch_plan_destroy(p);
+        return PALD_ERR_DEVICE;
+    }
+    *plan_out = p;
+    return PALD_OK;
 }
-size_t pald_batch_workspace_bytes(const pald_batch_plan *) { return 0; }
-int64_t pald_batch_total_elements(const pald_batch_plan *) { return 0; }
-int64_t pald_batch_offset(const pald_batch_plan *, int32_t) { return -1; }
-pald_status pald_cohesion_batched(const pald_batch_plan *, const float *, int32_t *, float *, void *, size_t,
-                                  void *) {
-    return PALD_ERR_UNSUPPORTED;
+
+size_t pald_batch_workspace_bytes(const pald_batch_plan *plan) { return plan ? plan->ws_bytes : 0; }
+
+int64_t pald_batch_total_elements(const pald_batch_plan *plan) { return plan ? plan->L.total_elems : -1; }
+
+int64_t pald_batch_offset(const pald_batch_plan *plan, int32_t i) {
+    if (!plan || i < 0 || i >= plan->count) return -1;
+    return plan->L.off[i];
 }
-void pald_batch_plan_destroy(pald_batch_plan *) {}
+
+int32_t pald_batch_grid(const pald_batch_plan *plan) { return plan ? plan->grid : -1; }
+
+pald_status pald_cohesion_batched(const pald_batch_plan *plan, const float *D_packed, int32_t *U_packed,
+                                  float *C_packed, void *ws, size_t ws_bytes, void *stream) {
+    if (!plan || !D_packed || !C_packed || !ws || ws_bytes < plan->ws_bytes) return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
+    return enqueue_batch(plan, D_packed, U_packed, C_packed, ws, (hipStream_t)stream);
 }
+
+pald_status pald_batch_timestamps(const pald_batch_plan *plan, const void *ws, void *stream, double *start_us,
+                                  double *end_us) {
+    if (!plan || !ws || !start_us || !end_us || !(plan->flags & PALD_BATCH_TIMESTAMPS)) return PALD_ERR_ARG;
+    std::vector<uint64_t> h((size_t)plan->count * 2);
+    hipStream_t s = (hipStream_t)stream;
+    const char *base = static_cast<const char *>(ws);
+    if (hipMemcpyAsync(h.data(), base + plan->off_stamps, h.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PALD_ERR_DEVICE;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, plan->device) != hipSuccess ||
+        rate_khz <= 0)
+        return PALD_ERR_DEVICE;
+    uint64_t t0 = ~0ull;
+    for (int32_t i = 0; i < plan->count; ++i) t0 = std::min(t0, h[2 * i]);
+    const double us_per_tick = 1000.0 / (double)rate_khz;
+    for (int32_t i = 0; i < plan->count; ++i) {
+        start_us[i] = (double)(h[2 * i] - t0) * us_per_tick;
+        end_us[i] = (double)(h[2 * i + 1] - t0) * us_per_tick;
+    }
+    return PALD_OK;
+}
+
+int64_t pald_batch_queue(int32_t count, const int64_t *n_host, const pald_batch_config *cfg, int32_t grid,
+                         int32_t *items_out, int64_t cap, int32_t *tiles1_out) {
+    BatchLayout L;
+    if (build_batch(count, n_host, cfg, grid, L) != PALD_OK) return -1;
+    const int64_t total = (int64_t)L.items.size();
+    if (items_out)
+        for (int64_t k = 0; k < total && k < cap; ++k) {
+            items_out[4 * k + 0] = L.items[k].x;
+            items_out[4 * k + 1] = L.items[k].y;
+            items_out[4 * k + 2] = L.items[k].z;
+            items_out[4 * k + 3] = L.items[k].w;
+        }
+    if (tiles1_out)
+        for (int32_t i = 0; i < count; ++i) tiles1_out[i] = L.mats[i].tiles1;
+    return total;
+}
+
+void pald_batch_plan_destroy(pald_batch_plan *plan) {
+    if (!plan) return;
+    if (plan->d_mats) (void)hipFree(plan->d_mats);
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    delete plan;
+}
+
+pald_status pald_batch_graph_create(const pald_batch_plan *plan, const float *D_packed, int32_t *U_packed,
+                                    float *C_packed, void *ws, size_t ws_bytes, pald_batch_graph **graph_out) {
+    if (!graph_out) return PALD_ERR_ARG;
+    *graph_out = nullptr;
+    if (!plan || !D_packed || !C_packed || !ws || ws_bytes < plan->ws_bytes) return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return PALD_ERR_DEVICE;
+    pald_batch_graph *g = new (std::nothrow) pald_batch_graph();
+    if (!g) {
+        (void)hipStreamDestroy(cs);
+        return PALD_ERR_NOMEM;
+    }
+    pald_status st = PALD_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = PALD_ERR_DEVICE;
+    if (st == PALD_OK) {
+        const pald_status est = enqueue_batch(plan, D_packed, U_packed, C_packed, ws, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (est != PALD_OK || ce != hipSuccess) {
+            st = PALD_ERR_DEVICE;
+            if (graph) (void)hipGraphDestroy(graph);
+        } else {
+            g->graph = graph;
+            if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) st = PALD_ERR_DEVICE;
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != PALD_OK) {
+        pald_batch_graph_destroy(g);
+        return st;
+    }
+    *graph_out = g;
+    return PALD_OK;
+}
+
+pald_status pald_batch_graph_launch(pald_batch_graph *graph, void *stream) {
+    if (!graph || !graph->exec) return PALD_ERR_ARG;
+    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? PALD_OK : PALD_ERR_DEVICE;
+}
+
+void pald_batch_graph_destroy(pald_batch_graph *graph) {
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+}
+
+}  // extern "C"

@@ -28,9 +28,13 @@ INPUT_FLAGS = {1: "nan", 2: "inf", 4: "negative", 8: "asymmetric", 16: "nonzero_
 EXPORTED = (
     "pald_status_string", "pald_version", "pald_workspace_bytes", "pald_focus_sizes",
     "pald_cohesion", "pald_check_input", "pald_batch_plan_create", "pald_batch_workspace_bytes",
-    "pald_batch_total_elements", "pald_batch_offset", "pald_cohesion_batched",
-    "pald_batch_plan_destroy", "pald_timings_collect",
+    "pald_batch_total_elements", "pald_batch_offset", "pald_batch_grid", "pald_cohesion_batched",
+    "pald_batch_timestamps", "pald_batch_queue", "pald_batch_plan_destroy",
+    "pald_batch_graph_create", "pald_batch_graph_launch", "pald_batch_graph_destroy",
+    "pald_timings_collect",
 )
+BATCH_MAX_BUCKETS = 8
+BATCH_TIMESTAMPS = 1
 
 
 class PaldError(RuntimeError):
@@ -48,6 +52,55 @@ class Options(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_int32 * 3),
     ]
+
+
+class BatchBucket(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int32), ("p1_tile", ctypes.c_int32),
+                ("y_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("nbuckets", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32),
+                ("queue_lag", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("bucket", BatchBucket * BATCH_MAX_BUCKETS)]
+
+
+def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int = 0,
+                      timestamps: bool = False) -> BatchConfig:
+    """buckets: list of (n_max, y_chunks) or dicts with keys n_max / y_chunks (p1_tile optional)."""
+    c = BatchConfig()
+    buckets = list(buckets or [])
+    if len(buckets) > BATCH_MAX_BUCKETS:
+        raise ValueError(f"at most {BATCH_MAX_BUCKETS} buckets")
+    for i, b in enumerate(buckets):
+        if isinstance(b, dict):
+            c.bucket[i].n_max = int(b["n_max"])
+            c.bucket[i].p1_tile = int(b.get("p1_tile", 0))
+            c.bucket[i].y_chunks = int(b.get("y_chunks", 1))
+        else:
+            c.bucket[i].n_max, c.bucket[i].y_chunks = int(b[0]), int(b[1])
+    c.nbuckets = len(buckets)
+    c.workgroups_per_cu = int(workgroups_per_cu)
+    c.queue_lag = int(queue_lag)
+    c.flags = BATCH_TIMESTAMPS if timestamps else 0
+    return c
+
+
+#: batched-mode settings written by paper_2307_16652_amd.tune for this GPU
+TUNING_PATH = os.path.join(PKG, "tuning", "batch_gfx950.json")
+
+
+def load_tuning(path: str | None = None, timestamps: bool = False) -> BatchConfig | None:
+    """The autotuned batched configuration, or None (library defaults) if none was written."""
+    import json
+
+    p = path or TUNING_PATH
+    if not os.path.exists(p):
+        return make_batch_config(timestamps=True) if timestamps else None
+    with open(p) as f:
+        data = json.load(f)
+    return make_batch_config(data.get("buckets"), data.get("workgroups_per_cu", 0), data.get("queue_lag", 0),
+                             timestamps)
 
 
 _lib = None
@@ -76,7 +129,8 @@ def load_library(path: str | None = None):
     lib.pald_cohesion.restype = i32
     lib.pald_check_input.argtypes = [vp, i64, i64, vp, sz, vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.pald_check_input.restype = i32
-    lib.pald_batch_plan_create.argtypes = [i32, ctypes.POINTER(i64), opt, ctypes.POINTER(vp)]
+    cfgp = ctypes.POINTER(BatchConfig)
+    lib.pald_batch_plan_create.argtypes = [i32, ctypes.POINTER(i64), cfgp, ctypes.POINTER(vp)]
     lib.pald_batch_plan_create.restype = i32
     lib.pald_batch_workspace_bytes.argtypes = [vp]
     lib.pald_batch_workspace_bytes.restype = sz
@@ -84,10 +138,24 @@ def load_library(path: str | None = None):
     lib.pald_batch_total_elements.restype = i64
     lib.pald_batch_offset.argtypes = [vp, i32]
     lib.pald_batch_offset.restype = i64
+    lib.pald_batch_grid.argtypes = [vp]
+    lib.pald_batch_grid.restype = i32
     lib.pald_cohesion_batched.argtypes = [vp, vp, vp, vp, vp, sz, vp]
     lib.pald_cohesion_batched.restype = i32
+    lib.pald_batch_timestamps.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]
+    lib.pald_batch_timestamps.restype = i32
+    lib.pald_batch_queue.argtypes = [i32, ctypes.POINTER(i64), cfgp, i32, ctypes.POINTER(i32), i64,
+                                     ctypes.POINTER(i32)]
+    lib.pald_batch_queue.restype = i64
     lib.pald_batch_plan_destroy.argtypes = [vp]
     lib.pald_batch_plan_destroy.restype = None
+    lib.pald_batch_graph_create.argtypes = [vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)]
+    lib.pald_batch_graph_create.restype = i32
+    lib.pald_batch_graph_launch.argtypes = [vp, vp]
+    lib.pald_batch_graph_launch.restype = i32
+    lib.pald_batch_graph_destroy.argtypes = [vp]
+    lib.pald_batch_graph_destroy.restype = None
     lib.pald_timings_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
     lib.pald_timings_collect.restype = i32
     if path is None:
@@ -218,22 +286,43 @@ def timings_collect() -> dict:
 # batched mode
 
 
+def batch_queue(sizes: Sequence[int], grid: int, config: BatchConfig | None = None):
+    """Host-only: the queue a batched plan would run, as (items [k, 4] int32, tiles1 [count])."""
+    import numpy as np
+
+    lib = load_library()
+    arr = (ctypes.c_int64 * len(sizes))(*[int(x) for x in sizes])
+    cfg = ctypes.byref(config) if config is not None else None
+    total = lib.pald_batch_queue(len(sizes), arr, cfg, int(grid), None, 0, None)
+    if total < 0:
+        raise PaldError(ERR_ARG, "pald_batch_queue")
+    items = np.empty((total, 4), dtype=np.int32)
+    tiles1 = np.empty(len(sizes), dtype=np.int32)
+    lib.pald_batch_queue(len(sizes), arr, cfg, int(grid),
+                         items.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), total,
+                         tiles1.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return items, tiles1
+
+
 class BatchPlan:
     """Plan for one packed batch of matrices of sizes `sizes` (see pald.h)."""
 
-    def __init__(self, sizes: Sequence[int], **opts):
+    def __init__(self, sizes: Sequence[int], config: BatchConfig | None = None):
         lib = load_library()
         self.sizes = [int(s) for s in sizes]
         arr = (ctypes.c_int64 * len(self.sizes))(*self.sizes)
-        o = make_options(**opts)
+        self.config = config
         h = ctypes.c_void_p()
-        st = lib.pald_batch_plan_create(len(self.sizes), arr, ctypes.byref(o), ctypes.byref(h))
+        st = lib.pald_batch_plan_create(len(self.sizes), arr,
+                                        ctypes.byref(config) if config is not None else None,
+                                        ctypes.byref(h))
         _check(st, "pald_batch_plan_create")
         self._h = h
         self._lib = lib
         self.total = int(lib.pald_batch_total_elements(h))
         self.offsets = [int(lib.pald_batch_offset(h, i)) for i in range(len(self.sizes))]
         self.ws_bytes = int(lib.pald_batch_workspace_bytes(h))
+        self.grid = int(lib.pald_batch_grid(h))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -247,9 +336,10 @@ class BatchPlan:
             pass
 
     def workspace(self, device):
-        return _torch().empty(max(self.ws_bytes, 256), dtype=_torch().uint8, device=device)
+        torch = _torch()
+        return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
 
-    def run(self, D_packed, U_packed=None, C_packed=None, ws=None, want_u: bool = True):
+    def _outputs(self, D_packed, U_packed, C_packed, ws, want_u):
         torch = _torch()
         if D_packed.dtype != torch.float32 or D_packed.numel() != self.total or not D_packed.is_cuda:
             raise ValueError("D_packed must be a flat float32 cuda tensor of sum(n_i^2) elements")
@@ -260,11 +350,31 @@ class BatchPlan:
             C_packed = torch.empty(self.total, dtype=torch.float32, device=dev)
         if ws is None:
             ws = self.workspace(dev)
+        return U_packed, C_packed, ws
+
+    def run(self, D_packed, U_packed=None, C_packed=None, ws=None, want_u: bool = True):
+        U_packed, C_packed, ws = self._outputs(D_packed, U_packed, C_packed, ws, want_u)
         st = self._lib.pald_cohesion_batched(
             self._h, D_packed.data_ptr(), U_packed.data_ptr() if U_packed is not None else None,
-            C_packed.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(dev))
+            C_packed.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(D_packed.device))
         _check(st, "pald_cohesion_batched")
         return U_packed, C_packed
+
+    def graph(self, D_packed, U_packed=None, C_packed=None, ws=None, want_u: bool = True):
+        """A captured hipGraph of one run with these buffers (see BatchGraph)."""
+        U_packed, C_packed, ws = self._outputs(D_packed, U_packed, C_packed, ws, want_u)
+        return BatchGraph(self, D_packed, U_packed, C_packed, ws)
+
+    def timestamps(self, ws):
+        """Per-matrix (start_us, end_us) of the last run, if the plan records them."""
+        import numpy as np
+
+        k = len(self.sizes)
+        a = (ctypes.c_double * k)()
+        b = (ctypes.c_double * k)()
+        st = self._lib.pald_batch_timestamps(self._h, ws.data_ptr(), _stream_ptr(ws.device), a, b)
+        _check(st, "pald_batch_timestamps")
+        return np.frombuffer(a, dtype=np.float64).copy(), np.frombuffer(b, dtype=np.float64).copy()
 
     def pack(self, mats):
         torch = _torch()
@@ -274,9 +384,38 @@ class BatchPlan:
         return [flat[o:o + s * s].view(s, s) for o, s in zip(self.offsets, self.sizes)]
 
 
-def cohesion_batched(mats, **opts):
+class BatchGraph:
+    """One batched run captured as a hipGraph; keeps its buffers alive."""
+
+    def __init__(self, plan: BatchPlan, D_packed, U_packed, C_packed, ws):
+        self.plan, self.D, self.U, self.C, self.ws = plan, D_packed, U_packed, C_packed, ws
+        h = ctypes.c_void_p()
+        st = plan._lib.pald_batch_graph_create(
+            plan._h, D_packed.data_ptr(), U_packed.data_ptr() if U_packed is not None else None,
+            C_packed.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.byref(h))
+        _check(st, "pald_batch_graph_create")
+        self._h = h
+
+    def launch(self):
+        st = self.plan._lib.pald_batch_graph_launch(self._h, _stream_ptr(self.D.device))
+        _check(st, "pald_batch_graph_launch")
+        return self.U, self.C
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.plan._lib.pald_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cohesion_batched(mats, config: BatchConfig | None = None):
     """[(U_i, C_i)] for a list of square float32 cuda matrices, in one batched launch."""
-    plan = BatchPlan([m.shape[0] for m in mats], **opts)
+    plan = BatchPlan([m.shape[0] for m in mats], config=config)
     try:
         Dp = plan.pack(mats)
         Up, Cp = plan.run(Dp)

@@ -1,0 +1,196 @@
+"""GPU parity of the batched persistent mode (one launch for many matrices)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_c_close, assert_u_equal, check_invariants, log
+from paper_2307_16652_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_16652_amd import pald
+
+    pald.load_library()
+
+
+def make_batch(sizes, seed=0, kind="mixture"):
+    mats = []
+    for i, n in enumerate(sizes):
+        if kind == "grid":
+            P = np.random.default_rng([seed, i]).integers(0, 4, size=(n, 3))
+            mats.append(synth.pairwise_distances(P, squared=True))
+        else:
+            mats.append(synth.pairwise_distances(synth.batch_points(i, int(n), seed=seed)))
+    return mats
+
+
+def run_batch(mats, config=None, want_u=True):
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    plan = pald.BatchPlan([m.shape[0] for m in mats], config=config)
+    Dp = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).cuda()
+    ws = plan.workspace(Dp.device)
+    Up, Cp = plan.run(Dp, ws=ws, want_u=want_u)
+    torch.cuda.synchronize()
+    Us = [u.cpu().numpy() for u in plan.unpack(Up)] if Up is not None else None
+    Cs = [c.cpu().numpy() for c in plan.unpack(Cp)]
+    return plan, ws, Us, Cs
+
+
+def check_all(mats, Us, Cs, every=1, what=""):
+    for i, D in enumerate(mats):
+        if i % every:
+            continue
+        Uo, Co = oracle.pald(D)
+        if Us is not None:
+            assert_u_equal(Us[i], Uo, f"{what} matrix {i} (n={D.shape[0]})")
+        assert_c_close(Cs[i], Co, what=f"{what} matrix {i} (n={D.shape[0]})")
+
+
+RAGGED = [2, 3, 5, 17, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 257, 300]
+
+
+def test_ragged_sizes():
+    mats = make_batch(RAGGED, seed=1)
+    log(f"[batched] ragged {RAGGED}")
+    _, _, Us, Cs = run_batch(mats)
+    check_all(mats, Us, Cs, what="ragged")
+
+
+def test_tie_heavy_and_duplicates():
+    sizes = [4, 9, 64, 70, 150]
+    mats = make_batch(sizes, seed=2, kind="grid")
+    _, _, Us, Cs = run_batch(mats)
+    check_all(mats, Us, Cs, what="grid")
+
+
+@pytest.mark.parametrize("chunks", [2, 3, 7])
+def test_y_split_tiles(chunks):
+    from paper_2307_16652_amd import pald
+
+    sizes = [40, 65, 130, 260, 33]
+    mats = make_batch(sizes, seed=3)
+    cfg = pald.make_batch_config([(50, 1), (1 << 30, chunks)])
+    log(f"[batched] y split {chunks}")
+    _, _, Us, Cs = run_batch(mats, config=cfg)
+    check_all(mats, Us, Cs, what=f"y_chunks={chunks}")
+
+
+@pytest.mark.parametrize("wpc,lag", [(1, 1), (2, 5), (4, 1)])
+def test_grid_and_lag_settings(wpc, lag):
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([90, 7, 200, 64, 150, 33], seed=4)
+    cfg = pald.make_batch_config(workgroups_per_cu=wpc, queue_lag=lag)
+    _, _, Us, Cs = run_batch(mats, config=cfg)
+    check_all(mats, Us, Cs, what=f"wpc={wpc} lag={lag}")
+
+
+def test_without_u():
+    mats = make_batch([50, 120], seed=5)
+    _, _, Us, Cs = run_batch(mats, want_u=False)
+    assert Us is None
+    check_all(mats, None, Cs, what="no U")
+
+
+def test_matches_single_matrix_path():
+    """Batched and single-matrix launches agree to the tolerance (different tilings)."""
+    from gpu_helpers import gpu_cohesion
+
+    mats = make_batch([100, 257], seed=6)
+    _, _, Us, Cs = run_batch(mats)
+    for D, U, C in zip(mats, Us, Cs):
+        U1, C1 = gpu_cohesion(D)
+        assert np.array_equal(U, U1)
+        np.testing.assert_allclose(C, C1, rtol=2e-6, atol=0)
+
+
+def test_deterministic_and_graph_replays():
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([77, 150, 3, 64, 201], seed=7)
+    cfg = pald.make_batch_config([(100, 1), (1 << 30, 2)])
+    plan = pald.BatchPlan([m.shape[0] for m in mats], config=cfg)
+    Dp = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).cuda()
+    ws = plan.workspace(Dp.device)
+    U1, C1 = plan.run(Dp, ws=ws)
+    U1, C1 = U1.clone(), C1.clone()
+    U2, C2 = plan.run(Dp, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2) and torch.equal(C1, C2), "two batched runs differ"
+    g = plan.graph(Dp)
+    for r in range(4):
+        g.C.fill_(-1.0)  # eager work between the replays
+        g.U.fill_(-1)
+        torch.cuda.synchronize()
+        Ug, Cg = g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, U1), f"graph replay {r}: U differs"
+        assert torch.equal(Cg, C1), f"graph replay {r}: C differs"
+        plan.run(Dp, ws=ws)  # eager batched run in between
+        torch.cuda.synchronize()
+    g.close()
+    Us = [u.cpu().numpy() for u in plan.unpack(U1)]
+    Cs = [c.cpu().numpy() for c in plan.unpack(C1)]
+    check_all(mats, Us, Cs, what="graph")
+
+
+def test_timestamps():
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([60, 130, 90], seed=8)
+    cfg = pald.make_batch_config(timestamps=True)
+    plan, ws, Us, Cs = run_batch(mats, config=cfg)
+    start, end = plan.timestamps(ws)
+    assert (start >= 0).all() and (end > start).all() and start.min() == 0
+    check_all(mats, Us, Cs, what="timestamps")
+    torch.cuda.synchronize()
+
+
+def test_unaligned_base_pointer():
+    """The packed arrays start 4 bytes past an aligned address."""
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([36, 64, 100], seed=9)
+    plan = pald.BatchPlan([m.shape[0] for m in mats])
+    flat = np.concatenate([m.reshape(-1) for m in mats])
+    buf = torch.zeros(flat.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(flat).cuda()
+    Dp = buf[1:]
+    Ub = torch.zeros(flat.size + 1, dtype=torch.int32, device="cuda")
+    Cb = torch.zeros(flat.size + 1, dtype=torch.float32, device="cuda")
+    Up, Cp = plan.run(Dp, U_packed=Ub[1:], C_packed=Cb[1:])
+    torch.cuda.synchronize()
+    check_all(mats, [u.cpu().numpy() for u in plan.unpack(Up)], [c.cpu().numpy() for c in plan.unpack(Cp)],
+              what="unaligned")
+
+
+def test_config_batch_2000_sampled():
+    """The 2000-matrix workload (n uniform in [32, 1024], 2-5 clusters in R^4):
+    oracle on every 20th matrix, invariants on all."""
+    import time
+
+    t0 = time.time()
+    ns = synth.batch_sizes()
+    mats = [synth.pairwise_distances(synth.batch_points(i, int(n))) for i, n in enumerate(ns)]
+    log(f"[batched] generated 2000 matrices in {time.time() - t0:.1f}s")
+    _, _, Us, Cs = run_batch(mats)
+    log("[batched] run done; checking")
+    check_all(mats, Us, Cs, every=20, what="batch2000")
+    for i in range(len(mats)):
+        check_invariants(Us[i], Cs[i], f"batch2000 matrix {i}")

@@ -46,19 +46,25 @@ struct BatchMatrix {
 constexpr int32_t ITEM_PASS1 = 0;
 constexpr int32_t ITEM_PASS2 = 1;
 
-constexpr int BATCH_THREADS = 256;
+#ifndef PALD_BATCH_THREADS
+#define PALD_BATCH_THREADS 256
+#endif
+#ifndef PALD_BATCH_MIN_BLOCKS
+#define PALD_BATCH_MIN_BLOCKS 2
+#endif
+constexpr int BATCH_THREADS = PALD_BATCH_THREADS;
 // One pass-1 shape (64 x 64 tiles, 2 x 8 counters per thread) and one pass-2
 // shape (64 x 64 tiles, 4 x 4 pairs): both inlined in one kernel, the larger
 // single-matrix pass-1 register tile would push the kernel to one wave per
 // SIMD.
-constexpr int BATCH_P1_T = 64;
-constexpr int BATCH_P2_T = 64, BATCH_P2_R = 4, BATCH_P2_KY = 16;
-using BatchP1 = Pass1Cfg<BATCH_P1_T, 2, 8, 16>;
-using BatchP2 = Pass2Cfg<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY>;
+constexpr int BATCH_P1_T = 64, BATCH_P1_RX = BATCH_THREADS == 256 ? 2 : 1;
+constexpr int BATCH_P2_T = 64, BATCH_P2_RX = BATCH_THREADS == 256 ? 4 : 2, BATCH_P2_KY = 16;
+using BatchP1 = Pass1Cfg<BATCH_P1_T, BATCH_P1_RX, 8, 16>;
+using BatchP2 = Pass2Cfg<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY>;
 static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS,
               "both batched tile shapes use one workgroup size");
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int BATCH_LDS_VEC = 2 * cmax(BatchP1::VEC_PER_CHUNK, BatchP2::VEC_PER_CHUNK);
+constexpr int BATCH_LDS_VEC = cmax(BatchP1::LDS_VEC, BatchP2::LDS_VEC);
 
 // Counter layout (uint32): [0] queue head, [1 .. count] pass-1 done counts,
 // [1 + count ..] per-tile arrival counters of split pass-2 tiles.
@@ -75,96 +81,110 @@ __global__ void batch_reset_kernel(uint32_t *__restrict__ ctr, int64_t nctr, uin
         }
 }
 
-__global__ __launch_bounds__(BATCH_THREADS) void batched_cohesion_kernel(
+__global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_cohesion_kernel(
     const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     int32_t *__restrict__ U, float *__restrict__ C, float *__restrict__ Wr, double *__restrict__ Pr,
     uint32_t *__restrict__ ctr, int32_t count, uint64_t *__restrict__ stamps, int32_t d_aligned) {
     __shared__ uint4 sm[BATCH_LDS_VEC];
+    // The current item and its matrix record live in LDS and are re-read after
+    // each tile: nothing has to stay in registers across the tile body.
     __shared__ int32_t s_item;
+    __shared__ int4 s_it;
+    __shared__ BatchMatrix s_m;
     __shared__ int32_t s_last;
     const int tid = threadIdx.x;
     uint32_t *const done1 = ctr + 1;
-    uint32_t *const arrive = ctr + 1 + count;
 
     for (;;) {
-        if (tid == 0) s_item = (int32_t)atomicAdd(&ctr[0], 1u);
-        __syncthreads();
-        const int32_t it = s_item;
-        __syncthreads();  // every thread has read s_item before it can change again
-        if (it >= total) break;
-
-        const int4 item = items[it];
-        const BatchMatrix m = mats[item.x];
-        const int64_t n = m.n;
-        const float *Dm = D + m.off;
-        float *Wm = Wr + m.woff;
-        const bool vec_d = d_aligned && m.vec_d;
-        if (stamps && tid == 0) atomicMin((unsigned long long *)&stamps[2 * item.x], (unsigned long long)wall_clock64());
-
-        if (item.y == ITEM_PASS1) {
-            int32_t bx, by;
-            tri_tile(item.z, bx, by);
-            int32_t *Um = U ? U + m.off : nullptr;
-            pass1_tile<BATCH_P1_T, 2, 8, 16>(sm, Dm, n, n, Um, n, Wm, m.ldw, bx, by, 0, n, false, vec_d);
-            __threadfence();  // release this thread's U / W stores at device scope
-            __syncthreads();
-            if (tid == 0) atomicAdd(&done1[item.x], 1u);
-        } else {
-            if (tid == 0) {
-                while (__hip_atomic_load(&done1[item.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                       (uint32_t)m.tiles1)
-                    __builtin_amdgcn_s_sleep(2);
-                __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        if (tid == 0) {
+            const int32_t it = (int32_t)atomicAdd(&ctr[0], 1u);
+            s_item = it;
+            if (it < total) {
+                s_it = items[it];
+                s_m = mats[s_it.x];
             }
-            __syncthreads();
-            __threadfence();  // acquire for every wave before reading the weights
-            int32_t bx, bz;
-            tri_tile(item.z, bx, bz);
-            const int64_t ybeg = (int64_t)item.w * m.y_per_chunk;
-            const int64_t yend = min(n, ybeg + (int64_t)m.y_per_chunk);
-            if (m.y_chunks == 1) {
-                Pass2Out out{C + m.off, n, nullptr, nullptr};
-                pass2_tile<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY, false>(sm, Dm, n, n, Wm, m.ldw, out, bx, bz, ybeg,
-                                                                       yend, vec_d, true);
-            } else {
-                constexpr int64_t TT2 = 2 * BATCH_P2_T * BATCH_P2_T;
-                double *tiles = Pr + m.poff + (int64_t)item.z * m.y_chunks * TT2;
-                Pass2Out out{nullptr, 0, nullptr, tiles + (int64_t)item.w * TT2};
-                pass2_tile<BATCH_P2_T, BATCH_P2_R, BATCH_P2_KY, false>(sm, Dm, n, n, Wm, m.ldw, out, bx, bz, ybeg,
-                                                                       yend, vec_d, true);
-                __threadfence();
+        }
+        __syncthreads();
+        if (s_item >= total) break;  // uniform: every thread reads the same value
+
+        {
+            const int32_t mi = s_it.x;
+            if (stamps && tid == 0)
+                atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
+            const int64_t n = s_m.n;
+            const bool vec_d = d_aligned && s_m.vec_d;
+            if (s_it.y == ITEM_PASS1) {
+                int32_t bx, by;
+                tri_tile(s_it.z, bx, by);
+                int32_t *Um = U ? U + s_m.off : nullptr;
+                pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(sm, D + s_m.off, n, n, Um, n, Wr + s_m.woff, s_m.ldw, bx, by, 0, n,
+                                                 false, vec_d);
+                __threadfence();  // release this thread's U / W stores at device scope
                 __syncthreads();
+                if (tid == 0) atomicAdd(&done1[s_it.x], 1u);
+            } else {
                 if (tid == 0) {
-                    const uint32_t prev = atomicAdd(&arrive[m.ctr2 + item.z], 1u);
-                    s_last = (prev == (uint32_t)(m.y_chunks - 1)) ? 1 : 0;
-                    if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                    while (__hip_atomic_load(&done1[mi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           (uint32_t)s_m.tiles1)
+                        __builtin_amdgcn_s_sleep(2);
+                    __atomic_thread_fence(__ATOMIC_ACQUIRE);
                 }
                 __syncthreads();
-                if (s_last) {
+                __threadfence();  // acquire for every wave before reading the weights
+                int32_t bx, bz;
+                tri_tile(s_it.z, bx, bz);
+                const int64_t ybeg = (int64_t)s_it.w * s_m.y_per_chunk;
+                const int64_t yend = min(n, ybeg + (int64_t)s_m.y_per_chunk);
+                constexpr int64_t TT2 = 2 * BATCH_P2_T * BATCH_P2_T;
+                Pass2Out out{nullptr, 0, nullptr, nullptr};
+                if (s_m.y_chunks == 1) {
+                    out.C = C + s_m.off;
+                    out.ldc = n;
+                } else {
+                    out.tile = Pr + s_m.poff + ((int64_t)s_it.z * s_m.y_chunks + s_it.w) * TT2;
+                }
+                pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false>(sm, D + s_m.off, n, n, Wr + s_m.woff, s_m.ldw,
+                                                                       out, bx, bz, ybeg, yend, vec_d, true);
+                if (s_m.y_chunks > 1) {
                     __threadfence();
-                    const int64_t X0 = (int64_t)bx * BATCH_P2_T, Z0 = (int64_t)bz * BATCH_P2_T;
-                    const double nm1 = (double)(n - 1);
-                    float *Cm = C + m.off;
-                    for (int e = tid; e < BATCH_P2_T * BATCH_P2_T; e += BATCH_THREADS) {
-                        const int i = e / BATCH_P2_T, j = e % BATCH_P2_T;
-                        const int64_t x = X0 + i, z = Z0 + j;
-                        if (x >= n || z >= n) continue;
-                        double sf = 0.0, sr = 0.0;
-                        for (int32_t k = 0; k < m.y_chunks; ++k) {
-                            sf += tiles[k * TT2 + e];
-                            sr += tiles[k * TT2 + BATCH_P2_T * BATCH_P2_T + e];
+                    __syncthreads();
+                    if (tid == 0) {
+                        const uint32_t prev = atomicAdd(&ctr[1 + count + s_m.ctr2 + s_it.z], 1u);
+                        s_last = (prev == (uint32_t)(s_m.y_chunks - 1)) ? 1 : 0;
+                        if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                    }
+                    __syncthreads();
+                    if (s_last) {
+                        __threadfence();
+                        const int64_t nn = s_m.n;
+                        const int32_t chunks = s_m.y_chunks;
+                        int32_t tbx, tbz;
+                        tri_tile(s_it.z, tbx, tbz);
+                        const int64_t X0 = (int64_t)tbx * BATCH_P2_T, Z0 = (int64_t)tbz * BATCH_P2_T;
+                        const double nm1 = (double)(nn - 1);
+                        const double *tiles = Pr + s_m.poff + (int64_t)s_it.z * chunks * TT2;
+                        float *Cm = C + s_m.off;
+                        for (int e = tid; e < BATCH_P2_T * BATCH_P2_T; e += BATCH_THREADS) {
+                            const int i = e / BATCH_P2_T, j = e % BATCH_P2_T;
+                            const int64_t x = X0 + i, z = Z0 + j;
+                            if (x >= nn || z >= nn) continue;
+                            double sf = 0.0, sr = 0.0;
+                            for (int32_t k = 0; k < chunks; ++k) {
+                                sf += tiles[k * TT2 + e];
+                                sr += tiles[k * TT2 + BATCH_P2_T * BATCH_P2_T + e];
+                            }
+                            Cm[x * nn + z] = (float)(sf / nm1);
+                            if (tbx != tbz) Cm[z * nn + x] = (float)(sr / nm1);
                         }
-                        Cm[x * n + z] = (float)(sf / nm1);
-                        if (bx != bz) Cm[z * n + x] = (float)(sr / nm1);
                     }
                 }
             }
+            if (stamps && tid == 0) {
+                __threadfence();
+                atomicMax((unsigned long long *)&stamps[2 * s_it.x + 1], (unsigned long long)wall_clock64());
+            }
         }
-        if (stamps && tid == 0) {
-            __threadfence();
-            atomicMax((unsigned long long *)&stamps[2 * item.x + 1], (unsigned long long)wall_clock64());
-        }
-        __syncthreads();  // LDS and s_last are reused by the next item
+        __syncthreads();  // LDS (tile buffers, s_item, s_it, s_m, s_last) is reused by the next item
     }
 }
 

@@ -99,7 +99,7 @@ __device__ __forceinline__ void focus_count8(int32_t (&c)[8], uint32_t x, const 
 // instructions after it is written (the wait states a vector read of a
 // vector-written scalar register needs) and the four pairs interleave; the
 // compiler's own schedule funnels the masks through one or two registers.
-// Registers only, no memory access.
+// Registers only, no memory access; EXEC is back to its entry value at exit.
 template <bool ASSIGN>
 __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], const uint32_t (&t)[4], uint32_t a,
                                                 const uint32_t (&b)[4], float wx, float whx, const float (&wz)[4],
@@ -156,26 +156,28 @@ __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], 
               [rr0] "=&v"(rr[0]), [rr1] "=&v"(rr[1]), [rr2] "=&v"(rr[2]), [rr3] "=&v"(rr[3]), PALD_T4_OPERANDS
             : PALD_T4_INPUTS);
     } else {
+        // Adds only in the lanes whose pair is in the focus: EXEC is narrowed to
+        // each pair's membership mask in turn and restored at the end, which
+        // spares the select-with-zero of every term.
+        uint64_t sv;
         asm(PALD_T4_HEAD
-            "v_cndmask_b32_e64 %[f0], 0, %[f0], %[i0]\n\t"
-            "v_cndmask_b32_e64 %[g0], 0, %[g0], %[i0]\n\t"
-            "v_cndmask_b32_e64 %[f1], 0, %[f1], %[i1]\n\t"
-            "v_cndmask_b32_e64 %[g1], 0, %[g1], %[i1]\n\t"
-            "v_cndmask_b32_e64 %[f2], 0, %[f2], %[i2]\n\t"
-            "v_cndmask_b32_e64 %[g2], 0, %[g2], %[i2]\n\t"
-            "v_cndmask_b32_e64 %[f3], 0, %[f3], %[i3]\n\t"
-            "v_cndmask_b32_e64 %[g3], 0, %[g3], %[i3]\n\t"
+            "s_and_saveexec_b64 %[sv], %[i0]\n\t"
             "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
             "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
+            "s_and_b64 exec, %[sv], %[i1]\n\t"
             "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
             "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
+            "s_and_b64 exec, %[sv], %[i2]\n\t"
             "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
             "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
+            "s_and_b64 exec, %[sv], %[i3]\n\t"
             "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
-            "v_add_f32 %[rr3], %[rr3], %[g3]"
+            "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
+            "s_mov_b64 exec, %[sv]"
             : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
-              [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), PALD_T4_OPERANDS
-            : PALD_T4_INPUTS);
+              [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS
+            : PALD_T4_INPUTS
+            : "scc");
     }
 #undef PALD_T4_HEAD
 #undef PALD_T4_OPERANDS
@@ -253,11 +255,12 @@ struct Pass1Cfg {
     static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(T % 4 == 0, "tile must be a multiple of 4");
     static_assert(RY == 8, "focus counting works on rows of 8 y");
+    static constexpr int LDS_VEC = 2 * VEC_PER_CHUNK;  // uint4 of LDS, double-buffered
 };
 
 // One pass-1 tile (bx, by), bx <= by, over the z range [zbeg, zend).  Called
 // by every thread of a workgroup of Pass1Cfg::NT threads; `sm` points to
-// 2 * VEC_PER_CHUNK uint4 of LDS.  U may be null in direct mode.
+// Pass1Cfg::LDS_VEC uint4 of LDS.  U may be null in direct mode.
 template <int T, int RX, int RY, int KZ>
 __device__ __forceinline__ void pass1_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            int32_t *__restrict__ U, int64_t ldu, float *__restrict__ W, int64_t ldw,
@@ -360,7 +363,7 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
     const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
     float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok) {
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
-    __shared__ uint4 sm[2 * Cfg::VEC_PER_CHUNK];
+    __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, by;
     tri_tile((int32_t)blockIdx.x, bx, by);
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
@@ -398,6 +401,7 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // One thread keeps both accumulators of its pairs and shares the membership
 // test between them.
 //
+// Each thread owns RX x 4 pairs (x, z).
 // Grid: blockIdx.x enumerates the upper-triangular T x T tiles (bx <= bz);
 // blockIdx.y is the y-chunk.  A tile with bx < bz writes C[X][Z] and C[Z][X];
 // a diagonal tile covers every ordered pair of its block once as (x, z) and
@@ -406,7 +410,8 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // partial[chunk][x][z] (ld n) for finalize_kernel.
 //
 // Per y the tile stages row y of D and of W restricted to the x range and to
-// the z range (a = d_yx, b = d_yz, W_yx, W_yz; D and W are symmetric).  Rows
+// the z range (a = d_yx, b = d_yz, W_yx, W_yz; D and W are symmetric), and
+// the halves W/2 computed once while staging.  Rows
 // y >= n, and rows past the chunk, stage W = 0 and so add nothing; the terms
 // y = x and y = z add nothing because W_xx = W_zz = 0.
 //
@@ -414,13 +419,17 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // (s_and), so no vector select waits on a mask written by the vector
 // instruction just before it.
 
-template <int T, int R, int KY>
+template <int T, int RX, int KY>
 struct Pass2Cfg {
-    static constexpr int TT = T / R;                    // threads along each side
-    static constexpr int NT = TT * TT;
-    static constexpr int ROW = 4 * T;                   // a | W_yx | b | W_yz
+    static constexpr int RZ = 4;                        // z per thread (the term block's width)
+    static constexpr int TX = T / RX;                   // threads along x
+    static constexpr int TZ = T / RZ;                   // threads along z
+    static constexpr int NT = TX * TZ;
+    static constexpr int ROW = 4 * T;                   // loaded per y: a | W_yx | b | W_yz
+    static constexpr int LDS_ROW = 6 * T;               // staged per y: ... | W_yx/2 | W_yz/2
     static constexpr int VEC_PER_CHUNK = KY * ROW / 4;
     static constexpr int VEC_PER_THREAD = VEC_PER_CHUNK / NT;
+    static constexpr int LDS_VEC = 2 * KY * LDS_ROW / 4; // uint4 of LDS, double-buffered
     static constexpr int RUN = 8;                       // float32 run length before a Kahan fold
     static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(KY % RUN == 0, "KY must be a multiple of the run length");
@@ -441,35 +450,36 @@ struct Pass2Out {
 
 // One pass-2 tile (bx, bz), bx <= bz, over the y range [ybeg, yend).  Called
 // by every thread of a workgroup of Pass2Cfg::NT threads; `sm` points to
-// 2 * VEC_PER_CHUNK uint4 of LDS.
-template <int T, int R, int KY, bool F64>
+// Pass2Cfg::LDS_VEC uint4 of LDS.
+template <int T, int RX, int KY, bool F64>
 __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            const float *__restrict__ W, int64_t ldw, Pass2Out out, int32_t bx,
                                            int32_t bz, int64_t ybeg, int64_t yend, bool vec_ok_d, bool vec_ok_w) {
-    using Cfg = Pass2Cfg<T, R, KY>;
+    using Cfg = Pass2Cfg<T, RX, KY>;
     const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
     const int tid = threadIdx.x;
-    const int tx = tid % Cfg::TT, tz = tid / Cfg::TT;
+    constexpr int RZ = Cfg::RZ;
+    const int tx = tid % Cfg::TX, tz = tid / Cfg::TX;
 
     // stationary keys t_ij = d_xz
-    uint32_t t[R][R];
+    uint32_t t[RX][RZ];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int64_t x = X0 + tx * R + i;
+    for (int i = 0; i < RX; ++i) {
+        const int64_t x = X0 + tx * RX + i;
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int64_t z = Z0 + tz * R + j;
+        for (int j = 0; j < RZ; ++j) {
+            const int64_t z = Z0 + tz * RZ + j;
             t[i][j] = (x < n && z < n) ? key_of(D[x * ldd + z]) : 0u;
         }
     }
 
     // forward (c_xz) and reverse (c_zx) accumulators
-    float sf[R][R], cf[R][R], rf[R][R], sr[R][R], cr[R][R], rr[R][R];
-    double af[R][R], ar[R][R];
+    float sf[RX][RZ], cf[RX][RZ], rf[RX][RZ], sr[RX][RZ], cr[RX][RZ], rr[RX][RZ];
+    double af[RX][RZ], ar[RX][RZ];
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int i = 0; i < RX; ++i)
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
+        for (int j = 0; j < RZ; ++j) {
             sf[i][j] = cf[i][j] = rf[i][j] = 0.0f;
             sr[i][j] = cr[i][j] = rr[i][j] = 0.0f;
             af[i][j] = ar[i][j] = 0.0;
@@ -493,7 +503,20 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) sm[buf * Cfg::VEC_PER_CHUNK + tid + k * Cfg::NT] = pre[k];
+        for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) {
+            const int v = tid + k * Cfg::NT;
+            const int r = v / (Cfg::ROW / 4);
+            const int g = v % (Cfg::ROW / 4);
+            const int seg = g / (T / 4);
+            uint4 *row = sm + buf * (Cfg::LDS_VEC / 2) + r * (Cfg::LDS_ROW / 4);
+            row[g] = pre[k];
+            if (seg == 1 || seg == 3) {  // W segment: also its halves, once per staged value
+                const uint4 w = pre[k];
+                row[T + (seg == 1 ? 0 : T / 4) + g % (T / 4)] =
+                    make_uint4(__float_as_uint(0.5f * __uint_as_float(w.x)), __float_as_uint(0.5f * __uint_as_float(w.y)),
+                               __float_as_uint(0.5f * __uint_as_float(w.z)), __float_as_uint(0.5f * __uint_as_float(w.w)));
+            }
+        }
     };
 
     const int64_t ny = yend - ybeg;
@@ -507,28 +530,31 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
     for (int64_t c = 0; c < nchunks; ++c) {
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) fetch(ybeg + (c + 1) * KY);
-        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * Cfg::VEC_PER_CHUNK);
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (Cfg::LDS_VEC / 2));
 #pragma unroll 1
         for (int y0 = 0; y0 < KY; y0 += Cfg::RUN) {
 #pragma unroll
             for (int yy = 0; yy < Cfg::RUN; ++yy) {
-                const uint32_t *row = s + (y0 + yy) * Cfg::ROW;
-                uint32_t av[R], bv[R];
-                float wx[R], whx[R], wz[R], whz[R];
+                const uint32_t *row = s + (y0 + yy) * Cfg::LDS_ROW;
+                uint32_t av[RX], bv[RZ];
+                float wx[RX], whx[RX], wz[RZ], whz[RZ];
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    av[i] = row[tx * R + i];
-                    wx[i] = __uint_as_float(row[T + tx * R + i]);
-                    whx[i] = 0.5f * wx[i];
-                    bv[i] = row[2 * T + tz * R + i];
-                    wz[i] = __uint_as_float(row[3 * T + tz * R + i]);
-                    whz[i] = 0.5f * wz[i];
+                for (int i = 0; i < RX; ++i) {
+                    av[i] = row[tx * RX + i];
+                    wx[i] = __uint_as_float(row[T + tx * RX + i]);
+                    whx[i] = __uint_as_float(row[4 * T + tx * RX + i]);
+                }
+#pragma unroll
+                for (int j = 0; j < RZ; ++j) {
+                    bv[j] = row[2 * T + tz * RZ + j];
+                    wz[j] = __uint_as_float(row[3 * T + tz * RZ + j]);
+                    whz[j] = __uint_as_float(row[5 * T + tz * RZ + j]);
                 }
                 if (F64) {
 #pragma unroll
-                    for (int i = 0; i < R; ++i)
+                    for (int i = 0; i < RX; ++i)
 #pragma unroll
-                        for (int j = 0; j < R; ++j) {
+                        for (int j = 0; j < RZ; ++j) {
                             const uint32_t tt = t[i][j];
                             const uint64_t in = lane_mask(tt <= av[i]) & lane_mask(tt <= bv[j]);
                             float vf = lane_bit(in) ? whx[i] : 0.0f;
@@ -540,18 +566,18 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
                         }
                 } else if (yy == 0) {
 #pragma unroll
-                    for (int i = 0; i < R; ++i) cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                    for (int i = 0; i < RX; ++i) cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < R; ++i) cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                    for (int i = 0; i < RX; ++i) cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
                 }
             }
             if (!F64) {
                 // Kahan fold of the finished runs: sum - comp tracks the exact total.
 #pragma unroll
-                for (int i = 0; i < R; ++i)
+                for (int i = 0; i < RX; ++i)
 #pragma unroll
-                    for (int j = 0; j < R; ++j) {
+                    for (int j = 0; j < RZ; ++j) {
                         float yk = rf[i][j] - cf[i][j];
                         float tk = sf[i][j] + yk;
                         cf[i][j] = (tk - sf[i][j]) - yk;
@@ -570,15 +596,15 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
     const double nm1 = (double)(n - 1);
     const bool mirror = bx != bz;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const int64_t x = X0 + tx * R + i;
+    for (int i = 0; i < RX; ++i) {
+        const int64_t x = X0 + tx * RX + i;
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int64_t z = Z0 + tz * R + j;
+        for (int j = 0; j < RZ; ++j) {
+            const int64_t z = Z0 + tz * RZ + j;
             const double tf = F64 ? af[i][j] : ((double)sf[i][j] - (double)cf[i][j]);
             const double tr = F64 ? ar[i][j] : ((double)sr[i][j] - (double)cr[i][j]);
             if (out.tile) {
-                const int li = tx * R + i, lj = tz * R + j;
+                const int li = tx * RX + i, lj = tz * RZ + j;
                 out.tile[li * T + lj] = tf;
                 out.tile[T * T + li * T + lj] = tr;
                 continue;
@@ -595,13 +621,13 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
     }
 }
 
-template <int T, int R, int KY, bool F64>
-__global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kernel(
+template <int T, int RX, int KY, bool F64>
+__global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT)) void pass2_cohesion_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
     float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
     int32_t vec_ok_d, int32_t vec_ok_w) {
-    using Cfg = Pass2Cfg<T, R, KY>;
-    __shared__ uint4 sm[2 * Cfg::VEC_PER_CHUNK];
+    using Cfg = Pass2Cfg<T, RX, KY>;
+    __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, bz;
     tri_tile((int32_t)blockIdx.x, bx, bz);
     const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
@@ -613,7 +639,7 @@ __global__ __launch_bounds__((Pass2Cfg<T, R, KY>::NT)) void pass2_cohesion_kerne
     } else {
         out.slab = partial + (int64_t)blockIdx.y * n * n;
     }
-    pass2_tile<T, R, KY, F64>(sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
+    pass2_tile<T, RX, KY, F64>(sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
 }
 
 // C_xz = fl32( sum_k partial[k][x][z] / (n-1) ), the only cross-tile reduction.

@@ -24,10 +24,13 @@ using namespace pald;
 // pass 1: 128 x 128 (x,y) tiles, 8 x 8 counters per thread, 16 z rows per stage
 constexpr int P1_T = 128, P1_RX = 8, P1_RY = 8, P1_KZ = 16;
 using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
-// pass 2: symmetric 64 x 64 (x,z) tiles, 4 x 4 pairs (both directions) per thread,
+// pass 2: symmetric 64 x 64 (x,z) tiles, P2_RX x 4 pairs (both directions) per thread,
 // 16 y rows per stage
-constexpr int P2_T = 64, P2_R = 4, P2_KY = 16;
-using P2 = Pass2Cfg<P2_T, P2_R, P2_KY>;
+#ifndef PALD_P2_RX
+#define PALD_P2_RX 4
+#endif
+constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = 16;
+using P2 = Pass2Cfg<P2_T, P2_RX, P2_KY>;
 
 constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
 constexpr size_t ALIGN = 256;
@@ -193,10 +196,10 @@ pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, in
     {
         ScopedTiming tm(timing, 2, s);
         if (f64)
-            pass2_cohesion_kernel<P2_T, P2_R, P2_KY, true>
+            pass2_cohesion_kernel<P2_T, P2_RX, P2_KY, true>
                 <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
         else
-            pass2_cohesion_kernel<P2_T, P2_R, P2_KY, false>
+            pass2_cohesion_kernel<P2_T, P2_RX, P2_KY, false>
                 <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }

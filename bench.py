@@ -153,6 +153,41 @@ def batched_bench(dev, reps: int = 3):
     }
 
 
+def variants_bench(dev, reps: int = 3):
+    """Pairwise vs triplet variant on the n = 4096 six-cluster mixture in R^8."""
+    import torch
+
+    from paper_2307_16652_amd import pald, synth
+
+    n = 4096
+    Dg = torch.from_numpy(synth.mixture8d(n=n)).to(dev)
+    out = {"workload": "mixture8d n=4096 seed 2"}
+    ref = None
+    for variant in ("pairwise", "triplet"):
+        ws = pald.workspace(n, dev, variant=variant)
+        U, C = pald.cohesion(Dg, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        pald.timings_collect()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pald.cohesion(Dg, variant=variant, ws=ws, out_u=U, out_c=C, timing=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        kt = pald.timings_collect()
+        out[variant] = {"ms_per_step": round(ms, 3),
+                        "triplet_comparisons_G_per_s": round(2.0 * n**3 / (ms / 1e3) / 1e9, 1),
+                        "kernels_ms": {k: round(v[0] / v[1], 3) for k, v in kt.items()}}
+        if ref is None:
+            ref = (U.clone(), C.clone())
+        else:
+            out["triplet_U_equal"] = bool(torch.equal(U, ref[0]))
+            rel = ((C.double() - ref[1].double()).abs() / ref[1].double().abs().clamp_min(1e-300))
+            rel = torch.where(ref[1] == 0, (C != 0).double(), rel)
+            out["triplet_vs_pairwise_max_rel"] = float(rel.max().item())
+        del ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +295,9 @@ def main():
             "compensated_vs_f64_max_rel": float(diff.max().item()),
         }
         del Cf
+    if not args.no_comparators:
+        extra["variants_n4096"] = variants_bench(dev)
+        progress(f"variants: {extra['variants_n4096']}")
     extra["pass1_focus_lane_ops_frac"] = round(p1_ops / (p1_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
 
     if not args.no_batched:

@@ -212,6 +212,73 @@ pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, in
     return PALD_OK;
 }
 
+// ---- triplet variant ---------------------------------------------------------
+struct TripletPlan {
+    int64_t tiles = 0, ldw = 0;
+    size_t off_w = 0, off_a = 0, off_u = 0, bytes = 0;
+};
+
+TripletPlan triplet_plan(int64_t n) {
+    TripletPlan t;
+    const int64_t nb = ceil_div(n, TRI_T);
+    t.tiles = nb * (nb + 1) / 2;
+    t.ldw = (int64_t)align_up((size_t)n, 64);
+    size_t off = 0;
+    t.off_w = off;
+    off = align_up(off + (size_t)n * (size_t)t.ldw * sizeof(float), ALIGN);
+    t.off_a = off;
+    off = align_up(off + (size_t)n * (size_t)n * sizeof(double), ALIGN);
+    t.off_u = off;
+    off = align_up(off + (size_t)n * (size_t)n * sizeof(int32_t), ALIGN);
+    t.bytes = off;
+    return t;
+}
+
+size_t triplet_workspace_bytes(int64_t n) { return triplet_plan(n).bytes; }
+
+// Triplet pass 1 into U (initialised here).
+pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, hipStream_t s,
+                          bool timing) {
+    const TripletPlan t = triplet_plan(n);
+    if (t.tiles > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    triplet_init_u_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, U, ldu);
+    if (pald_status st = launch_status(); st != PALD_OK) return st;
+    ScopedTiming tm(timing, 5, s);
+    const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
+    triplet_kernel<false><<<(unsigned)t.tiles, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0);
+    return launch_status();
+}
+
+pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
+                             void *ws, size_t ws_bytes, hipStream_t s, bool timing) {
+    const TripletPlan t = triplet_plan(n);
+    if (ws_bytes < t.bytes) return PALD_ERR_ARG;
+    char *base = static_cast<char *>(ws);
+    float *W = reinterpret_cast<float *>(base + t.off_w);
+    double *A = reinterpret_cast<double *>(base + t.off_a);
+    int32_t *Ub = U;
+    int64_t ldub = ldu;
+    if (!Ub) {
+        Ub = reinterpret_cast<int32_t *>(base + t.off_u);
+        ldub = n;
+    }
+    if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
+    const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+    weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, t.ldw, n);
+    if (pald_status st = launch_status(); st != PALD_OK) return st;
+    triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A);
+    if (pald_status st = launch_status(); st != PALD_OK) return st;
+    {
+        ScopedTiming tm(timing, 6, s);
+        const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
+        triplet_kernel<true><<<(unsigned)t.tiles, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    ScopedTiming tm(timing, 7, s);
+    triplet_finalize_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(A, n, C, ldc);
+    return launch_status();
+}
+
 }  // namespace
 
 // ============================================================================
@@ -245,6 +312,8 @@ pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd, int32_t *U,
     Opts o;
     if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
     if (!D || !U || n < 2 || ldd < n || ldu < n) return PALD_ERR_ARG;
+    if (o.variant == PALD_VARIANT_TRIPLET)
+        return triplet_focus(D, n, ldd, U, ldu, (hipStream_t)stream, (o.flags & PALD_FLAG_TIMING) != 0);
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
     return run_pass1(D, n, ldd, U, ldu, nullptr, p.ldw, p, (hipStream_t)stream, (o.flags & PALD_FLAG_TIMING) != 0);
@@ -258,8 +327,10 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
-    if (o.variant == PALD_VARIANT_TRIPLET)
-        return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, o.accum == PALD_ACC_F64, timing);
+    if (o.variant == PALD_VARIANT_TRIPLET) {
+        if (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
+        return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, timing);
+    }
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
     if (ws_bytes < p.bytes) return PALD_ERR_ARG;

@@ -225,12 +225,12 @@ def workspace(n: int, device, **opts):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def focus_sizes(D, *, z_chunks: int = 0, timing: bool = False, out=None):
+def focus_sizes(D, *, variant: str = "auto", z_chunks: int = 0, timing: bool = False, out=None):
     """U (int32, n x n): local focus sizes of distance matrix D."""
     torch = _torch()
     n, ldd = _check_matrix(D)
     U = out if out is not None else torch.empty((n, n), dtype=torch.int32, device=D.device)
-    o = make_options(z_chunks=z_chunks, timing=timing)
+    o = make_options(variant=variant, z_chunks=z_chunks, timing=timing)
     st = load_library().pald_focus_sizes(D.data_ptr(), n, ldd, U.data_ptr(), U.stride(0),
                                          _stream_ptr(D.device), ctypes.byref(o))
     _check(st, "pald_focus_sizes")

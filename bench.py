@@ -47,7 +47,7 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(D: np.ndarray, target_s: float = 12.0):
+def cpu_baseline(D: np.ndarray, workload: str = "grid3d", target_s: float = 12.0):
     """Oracle throughput on the host cores for a bounded row sample of D."""
     import oracle
 
@@ -72,7 +72,7 @@ def cpu_baseline(D: np.ndarray, target_s: float = 12.0):
         "unit": "G triplet comparisons/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{k} random rows of U and C of the n={n} grid3d matrix (2*n^2 terms per row), "
+        "sample": f"{k} random rows of U and C of the n={n} {workload} matrix (2*n^2 terms per row), "
                   f"{t:.1f} s wall",
     }
 
@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=N, help="matrix size (default 16384)")
+    ap.add_argument("--workload", default="grid3d", choices=["grid3d", "aniso16d", "mixture8d", "uniform2d"],
+                    help="synthetic point cloud (default: the 16384-point integer grid)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-matrix batched measurement")
@@ -230,9 +232,14 @@ def main():
         torch.cuda.synchronize()
         progress("copy calibration: one elementwise kernel, 1 GiB read + 1 GiB written")
         del src, dst
-    progress(f"generating grid3d n={n} seed={SEED}")
-    D = synth.grid3d(n=n, seed=SEED)
-    Dg = torch.from_numpy(D).to(dev)
+    seed = {"grid3d": SEED, "aniso16d": 5, "mixture8d": 2, "uniform2d": 1}[args.workload]
+    progress(f"generating {args.workload} n={n} seed={seed}")
+    if args.workload == "aniso16d":
+        Dg = synth.pairwise_distances_torch(synth.aniso16d_points(n=n, seed=seed), device=dev)
+        D = None
+    else:
+        D = synth.workload(args.workload, n=n, seed=seed)
+        Dg = torch.from_numpy(D).to(dev)
     ws = pald.workspace(n, dev)
     U = torch.empty((n, n), dtype=torch.int32, device=dev)
     C = torch.empty((n, n), dtype=torch.float32, device=dev)
@@ -259,8 +266,10 @@ def main():
     value = terms / (ms_per_step / 1e3) / 1e9
     progress(f"{ms_per_step:.1f} ms/step, {value:.1f} G/s; kernels {kt}")
 
-    p2_ms = kt["pass2_cohesion"][0] / kt["pass2_cohesion"][1]
-    p1_ms = kt["pass1_focus"][0] / kt["pass1_focus"][1]
+    # per-step kernel time (a large grid runs as several launches per step)
+    p2_ms = kt["pass2_cohesion"][0] / args.steps
+    p1_ms = kt["pass1_focus"][0] / args.steps
+    p2_launches = kt["pass2_cohesion"][1] // args.steps
     p2_ops = PASS2_OPS_PER_TERM * n * n * (n - 1)
     p2_achieved = p2_ops / (p2_ms / 1e3) / 1e12
     p1_ops = PASS1_OPS_PER_TERM * (n * (n + 1) / 2) * n
@@ -273,8 +282,9 @@ def main():
         "traffic": None,
         "kernel": "pass2_cohesion",
         "kernel_ms": round(p2_ms, 3),
+        "launches_per_step": p2_launches,
     }
-    kernels = {k: round(v[0] / v[1], 3) for k, v in kt.items()}
+    kernels = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
 
     extra = {}
     if not args.no_comparators:
@@ -309,10 +319,10 @@ def main():
     base = None
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle rows)")
-        base = cpu_baseline(D)
+        base = cpu_baseline(D if D is not None else Dg.cpu().numpy(), args.workload)
 
     out = {
-        "metric": "triplet comparisons/sec (G/s) + % VALU peak, n=16384 fp32; batched matrices/sec",
+        "metric": f"triplet comparisons/sec (G/s) + % VALU peak, n={n} fp32; batched matrices/sec",
         "value": round(value, 2),
         "unit": "G triplet comparisons/s",
         "n_gpus": 1,
@@ -324,8 +334,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "grid3d", "n": n, "seed": SEED,
-                   "points": "uniform in {0..31}^3", "distance": "squared euclidean (integer, fp32)",
+        "config": {"workload": args.workload, "n": n, "seed": seed,
+                   "points": {"grid3d": "uniform in {0..31}^3",
+                              "aniso16d": "50 anisotropic rotated Gaussians in R^16",
+                              "mixture8d": "6 Gaussian clusters in R^8, sizes 1:2:...:32",
+                              "uniform2d": "uniform in [0,1]^2"}[args.workload],
+                   "distance": "squared euclidean (integer, fp32)" if args.workload == "grid3d"
+                   else "euclidean (fp32)",
                    "accumulation": "fp32 runs + Kahan partials, fp64 final reduce"},
         "roofline": roofline,
         "cpu_baseline": base,

@@ -239,8 +239,8 @@ __device__ __forceinline__ float weight_of(int32_t u) { return (float)(1.0 / (do
 // ---------------------------------------------------------------------------
 // Pass 1: focus sizes.
 //
-// Grid: blockIdx.x enumerates the upper-triangular tiles (bx <= by) of T x T
-// tiles; blockIdx.y is the z-chunk.  With one z-chunk the tile writes U (and,
+// Grid: tile0 + blockIdx.x enumerates the upper-triangular tiles (bx <= by) of
+// T x T tiles (large grids are launched in pieces); blockIdx.y is the z-chunk.  With one z-chunk the tile writes U (and,
 // if W != nullptr, the weights W) directly; with several it atomically adds
 // its counts into U, which must be zero on entry.
 
@@ -361,11 +361,11 @@ __device__ __forceinline__ void pass1_tile(uint4 *sm, const float *__restrict__ 
 template <int T, int RX, int RY, int KZ>
 __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
-    float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok) {
+    float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok, int32_t tile0) {
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
     __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, by;
-    tri_tile((int32_t)blockIdx.x, bx, by);
+    tri_tile(tile0 + (int32_t)blockIdx.x, bx, by);
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
     pass1_tile<T, RX, RY, KZ>(sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
@@ -402,8 +402,8 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // test between them.
 //
 // Each thread owns RX x 4 pairs (x, z).
-// Grid: blockIdx.x enumerates the upper-triangular T x T tiles (bx <= bz);
-// blockIdx.y is the y-chunk.  A tile with bx < bz writes C[X][Z] and C[Z][X];
+// Grid: tile0 + blockIdx.x enumerates the upper-triangular T x T tiles
+// (bx <= bz; large grids are launched in pieces); blockIdx.y is the y-chunk.  A tile with bx < bz writes C[X][Z] and C[Z][X];
 // a diagonal tile covers every ordered pair of its block once as (x, z) and
 // writes only C[x][z].  With one y-chunk the tile writes
 // C = fl32(sum / (n-1)); otherwise it writes float64 partial sums
@@ -625,11 +625,11 @@ template <int T, int RX, int KY, bool F64>
 __global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT)) void pass2_cohesion_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
     float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
-    int32_t vec_ok_d, int32_t vec_ok_w) {
+    int32_t vec_ok_d, int32_t vec_ok_w, int32_t tile0) {
     using Cfg = Pass2Cfg<T, RX, KY>;
     __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, bz;
-    tri_tile((int32_t)blockIdx.x, bx, bz);
+    tri_tile(tile0 + (int32_t)blockIdx.x, bx, bz);
     const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
     const int64_t yend = min(n, ybeg + (int64_t)y_per_chunk);
     Pass2Out out{nullptr, 0, nullptr, nullptr};

@@ -33,6 +33,11 @@ constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = 16;
 using P2 = Pass2Cfg<P2_T, P2_RX, P2_KY>;
 
 constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
+// Large tile grids are launched in pieces so that no single dispatch runs for
+// more than a few seconds (n = 65536: about 2-3 s per piece).
+constexpr int64_t P1_TILES_PER_LAUNCH = 32768;
+constexpr int64_t P2_TILES_PER_LAUNCH = 65536;
+constexpr int64_t TRI_TILES_PER_LAUNCH = 8192;
 constexpr size_t ALIGN = 256;
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -163,10 +168,14 @@ pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_
                       int64_t ldw, const Plan &p, hipStream_t s, bool timing) {
     const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     if (p.z_chunks == 1) {
-        ScopedTiming tm(timing, 0, s);
-        pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ>
-            <<<dim3((unsigned)p.tiles1, 1), P1::NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec);
-        return launch_status();
+        for (int64_t t0 = 0; t0 < p.tiles1; t0 += P1_TILES_PER_LAUNCH) {
+            ScopedTiming tm(timing, 0, s);
+            const unsigned g = (unsigned)std::min<int64_t>(P1_TILES_PER_LAUNCH, p.tiles1 - t0);
+            pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ>
+                <<<dim3(g, 1), P1::NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec, (int32_t)t0);
+            if (pald_status st = launch_status(); st != PALD_OK) return st;
+        }
+        return PALD_OK;
     }
     {
         const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
@@ -176,7 +185,7 @@ pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_
     {
         ScopedTiming tm(timing, 0, s);
         pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1::NT, 0, s>>>(
-            D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec);
+            D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     if (W) {
@@ -192,15 +201,15 @@ pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, in
                       int64_t ldc, double *part, const Plan &p, bool f64, hipStream_t s, bool timing) {
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     const int vecw = (aligned16(W) && ldw % 4 == 0) ? 1 : 0;
-    const dim3 grid((unsigned)p.tiles2, (unsigned)p.y_chunks);
-    {
+    for (int64_t t0 = 0; t0 < p.tiles2; t0 += P2_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 2, s);
+        const dim3 grid((unsigned)std::min<int64_t>(P2_TILES_PER_LAUNCH, p.tiles2 - t0), (unsigned)p.y_chunks);
         if (f64)
             pass2_cohesion_kernel<P2_T, P2_RX, P2_KY, true>
-                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw, (int32_t)t0);
         else
             pass2_cohesion_kernel<P2_T, P2_RX, P2_KY, false>
-                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw);
+                <<<grid, P2::NT, 0, s>>>(D, n, ldd, W, ldw, C, ldc, part, p.y_per_chunk, vecd, vecw, (int32_t)t0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     if (p.y_chunks > 1) {
@@ -243,10 +252,14 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     if (t.tiles > INT32_MAX) return PALD_ERR_UNSUPPORTED;
     triplet_init_u_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, U, ldu);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
-    ScopedTiming tm(timing, 5, s);
     const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
-    triplet_kernel<false><<<(unsigned)t.tiles, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0);
-    return launch_status();
+    for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
+        ScopedTiming tm(timing, 5, s);
+        const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
+        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0, (int32_t)t0);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    return PALD_OK;
 }
 
 pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
@@ -268,10 +281,11 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
-    {
+    const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
+    for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 6, s);
-        const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
-        triplet_kernel<true><<<(unsigned)t.tiles, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1);
+        const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
+        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1, (int32_t)t0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     ScopedTiming tm(timing, 7, s);

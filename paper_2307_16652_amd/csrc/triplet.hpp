@@ -129,7 +129,8 @@ template <bool PASS2>
 __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__restrict__ D, int64_t n, int64_t ldd,
                                                               const float *__restrict__ W, int64_t ldw,
                                                               int32_t *__restrict__ U, int64_t ldu,
-                                                              double *__restrict__ A, int32_t vec_d, int32_t vec_w) {
+                                                              double *__restrict__ A, int32_t vec_d, int32_t vec_w,
+                                                              int32_t tile0) {
     constexpr int T = TRI_T, R = TRI_R, KQ = TRI_KQ, NT = TRI_THREADS;
     constexpr int ROW = PASS2 ? 4 * T : 2 * T;     // loaded per q: a | (W_qp) | c | (W_qr)
     constexpr int LDS_ROW = PASS2 ? 6 * T : 2 * T; // staged: ... | W_qp/2 | W_qr/2
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
     __shared__ Part qbuf[4][KQ][T][PASS2 ? 2 : 1];  // per-wave (q, r) partials of one stage
 
     int32_t bx, bz;
-    tri_tile((int32_t)blockIdx.x, bx, bz);
+    tri_tile(tile0 + (int32_t)blockIdx.x, bx, bz);
     const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
     const int tid = threadIdx.x;
     const int tx = tid / 16, tz = tid % 16, wave = tid / 64, row = (tid % 64) / 16;

@@ -1,0 +1,78 @@
+"""The large single matrix: n = 65536 points in R^16 (50 anisotropic Gaussians),
+D = 17 GB in HBM, full U and C on one GPU.  Oracle on sampled rows; the global
+invariants (U symmetric, 2 <= U_xy <= n, sum C = n/2) on everything."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_c_close, assert_u_equal, log
+from paper_2307_16652_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N = 65536
+ORACLE_ROWS = 32
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    free, _ = torch.cuda.mem_get_info()
+    if free < 90e9:
+        pytest.skip("needs ~90 GB of free device memory")
+    from paper_2307_16652_amd import pald
+
+    pald.load_library()
+
+
+def test_config_aniso16d_n65536():
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    t0 = time.time()
+    P = synth.aniso16d_points(n=N)
+    D = synth.pairwise_distances_torch(P, device="cuda")
+    torch.cuda.synchronize()
+    log(f"[large] generated D ({N}x{N}) on the GPU in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    U, C = pald.cohesion(D)
+    torch.cuda.synchronize()
+    log(f"[large] pald_cohesion n={N}: {time.time() - t0:.1f}s")
+
+    # global invariants, in row blocks
+    total = 0.0
+    blk = 2048
+    for r0 in range(0, N, blk):
+        r1 = min(N, r0 + blk)
+        Ub = U[r0:r1]
+        assert torch.equal(Ub, U[:, r0:r1].T), f"U not symmetric in rows {r0}:{r1}"
+        off = torch.ones_like(Ub, dtype=torch.bool)
+        off[:, r0:r1].fill_diagonal_(False)
+        assert int(Ub[off].min()) >= 2 and int(Ub[off].max()) <= N
+        Cb = C[r0:r1]
+        assert bool((Cb >= 0).all())
+        depth = Cb.double().sum(dim=1)
+        assert float(depth.max()) <= 1 + 1e-5
+        total += float(depth.sum())
+    assert abs(total - N / 2) <= 1e-6 * N / 2, f"sum(C) = {total!r}, expected {N / 2}"
+    log(f"[large] invariants ok, sum(C) = {total:.6f}")
+
+    # oracle rows (the oracle needs all of D on the host)
+    rows = np.sort(np.random.default_rng(5).choice(N, size=ORACLE_ROWS, replace=False))
+    t0 = time.time()
+    Dh = D.cpu().numpy()
+    Ug = U[torch.from_numpy(rows).cuda()].cpu().numpy()
+    Cg = C[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del U, C, D
+    torch.cuda.empty_cache()
+    Uo, Co = oracle.pald_rows(Dh, rows)
+    log(f"[large] oracle on {ORACLE_ROWS} rows: {time.time() - t0:.1f}s")
+    assert_u_equal(Ug, Uo, "aniso16d n=65536")
+    err = assert_c_close(Cg, Co, what="aniso16d n=65536")
+    log(f"[large] max rel err {err:.3e}")

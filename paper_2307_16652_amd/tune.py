@@ -1,0 +1,149 @@
+"""Autotuner of the batched mode.
+
+    python -m paper_2307_16652_amd.tune [--out PATH] [--reps 3]
+
+Searches, on the 2000-matrix batch (n uniform in [32, 1024], 2-5 Gaussian
+clusters in R^4), for
+
+* the pass-2 y-split depth of each size bucket (splitting a large matrix's
+  pass-2 tiles over y shortens the items at the end of the queue),
+* the persistent grid size (workgroups per CU), and
+* the queue lag (how far a matrix's pass-2 items trail its pass-1 items),
+
+by coordinate descent on the measured time of one whole batched launch
+(median of `reps` graph replays), and writes the winner to
+tuning/batch_gfx950.json, which `pald.load_tuning()` (and so `bench.py`)
+picks up.  The tile shapes of the batched kernel are fixed at build time by
+its register budget; they are not part of this search.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+BUCKETS = (128, 256, 512, 1 << 30)
+Y_CHUNKS = (1, 2, 3, 4)
+LAGS = (1, 2, 4, 8)
+WPC = (1, 2)
+
+
+def log(msg):
+    print(f"[tune] {msg}", file=sys.stderr, flush=True)
+
+
+class Batch:
+    def __init__(self, dev, seed: int = 4):
+        import torch
+
+        from . import pald, synth
+
+        self.pald = pald
+        self.torch = torch
+        self.ns = [int(n) for n in synth.batch_sizes(seed=seed)]
+        t0 = time.time()
+        flat = np.concatenate([synth.pairwise_distances(synth.batch_points(i, n, seed=seed)).reshape(-1)
+                               for i, n in enumerate(self.ns)])
+        self.D = torch.from_numpy(flat).to(dev)
+        log(f"generated {len(self.ns)} matrices in {time.time() - t0:.1f}s")
+        self.ref = None
+
+    def time(self, cfg, reps: int) -> float:
+        torch, pald = self.torch, self.pald
+        plan = pald.BatchPlan(self.ns, config=cfg)
+        try:
+            ws = plan.workspace(self.D.device)
+            U = torch.empty(plan.total, dtype=torch.int32, device=self.D.device)
+            C = torch.empty(plan.total, dtype=torch.float32, device=self.D.device)
+            plan.run(self.D, U, C, ws)
+            g = plan.graph(self.D, U, C, ws)
+            g.launch()
+            torch.cuda.synchronize()
+            if self.ref is None:
+                self.ref = (U.clone(), C.clone())
+            elif not torch.equal(U, self.ref[0]) or not torch.allclose(C, self.ref[1], rtol=2e-6, atol=0):
+                raise RuntimeError("a tuning candidate changed the results")
+            times = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                g.launch()
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            g.close()
+            return float(np.median(times))
+        finally:
+            plan.close()
+
+
+def config_of(pald, chunks, wpc, lag):
+    return pald.make_batch_config([(b, c) for b, c in zip(BUCKETS, chunks)], workgroups_per_cu=wpc, queue_lag=lag)
+
+
+def tune(reps: int = 3, out: str | None = None) -> dict:
+    import torch
+
+    from . import pald
+
+    pald.load_library()
+    dev = torch.device("cuda:0")
+    batch = Batch(dev)
+    chunks = [1] * len(BUCKETS)
+    wpc, lag = 0, 0
+    best = batch.time(config_of(pald, chunks, wpc, lag), reps)
+    log(f"defaults: {best:.3f} ms")
+    trials = [{"chunks": list(chunks), "wpc": wpc, "lag": lag, "ms": best}]
+
+    def consider(c, w, l):
+        nonlocal best, chunks, wpc, lag
+        ms = batch.time(config_of(pald, c, w, l), reps)
+        trials.append({"chunks": list(c), "wpc": w, "lag": l, "ms": ms})
+        log(f"chunks={c} wpc={w} lag={l}: {ms:.3f} ms")
+        if ms < best * 0.995:
+            best, chunks, wpc, lag = ms, list(c), w, l
+
+    for w in WPC:
+        for l in LAGS:
+            consider(chunks, w, l)
+    for _ in range(2):  # two sweeps of coordinate descent over the buckets
+        for b in reversed(range(len(BUCKETS))):
+            for c in Y_CHUNKS:
+                if c != chunks[b]:
+                    cand = list(chunks)
+                    cand[b] = c
+                    consider(cand, wpc, lag)
+    result = {
+        "arch": "gfx950",
+        "workload": "2000 matrices, n uniform in [32, 1024], 2-5 Gaussian clusters in R^4, seed 4",
+        "buckets": [{"n_max": b, "y_chunks": c} for b, c in zip(BUCKETS, chunks)],
+        "workgroups_per_cu": wpc,
+        "queue_lag": lag,
+        "ms_per_batch": round(best, 3),
+        "default_ms_per_batch": round(trials[0]["ms"], 3),
+        "trials": trials,
+    }
+    path = out or pald.TUNING_PATH
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(result, f, indent=1)
+    log(f"best {best:.3f} ms -> {path}")
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser(description="autotune the batched PaLD mode")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    r = tune(args.reps, args.out)
+    print(json.dumps({k: v for k, v in r.items() if k != "trials"}))
+
+
+if __name__ == "__main__":
+    main()

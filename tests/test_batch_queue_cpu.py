@@ -134,3 +134,18 @@ def test_bad_batch_arguments():
     bad = pald.make_batch_config([(100, 0)])
     with pytest.raises(pald.PaldError):
         pald.batch_queue([10], grid=4, config=bad)
+
+
+def test_tuning_table_loads_into_a_valid_config():
+    """The autotuner's table (if present) parses and the host queue builder accepts it."""
+    import os
+
+    cfg = pald.load_tuning()
+    if not os.path.exists(pald.TUNING_PATH):
+        assert cfg is None
+        return
+    assert cfg is not None and 1 <= cfg.nbuckets <= pald.BATCH_MAX_BUCKETS
+    items, tiles1 = pald.batch_queue([40, 300, 1000], grid=512, config=cfg)
+    assert len(items) > 0 and (tiles1 > 0).all()
+    tcfg = pald.load_tuning(timestamps=True)
+    assert tcfg.flags == pald.BATCH_TIMESTAMPS

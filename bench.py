@@ -13,11 +13,13 @@ point in each of the two defining sums) divided by the time per step.
 
 `roofline` describes the dominant kernel (pass 2, cohesion), whose launches
 are timed with HIP events on the stream they run on.  Its algorithmic work is
-5 VALU lane-operations per cohesion term (x, y, z), y != x: for an unordered
-pair {x, z} and a second point y the two terms of c_xz and c_zx need one min,
-three compares, four selects and two adds, i.e. 10 operations for 2 terms;
-5 n^2 (n-1) per launch.  It is set against the VALU issue peak of
-256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s.
+4 VALU lane-operations per cohesion term (x, y, z), y != x -- the paper's
+count for the cohesion loop, three comparisons and one accumulate per pair
+and third point (Section 4, Thm 1) -- i.e. 4 n^2 (n-1) per step, set against
+the VALU issue peak of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T
+lane-ops/s.  `traffic` is the HBM bytes per launch measured by rocprofv3
+(profiles/*.traffic.json), reported only while the kernel source is the one
+that was profiled.
 
 `cpu_baseline` is the FP64 oracle on the host cores for a bounded sample of
 rows of the same matrix (2 n^2 comparison terms per row).
@@ -39,8 +41,24 @@ if ROOT not in sys.path:
 N = 16384
 SEED = 3
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3216 T lane-ops/s
-PASS2_OPS_PER_TERM = 5
+PASS2_OPS_PER_TERM = 4
 PASS1_OPS_PER_TERM = 3
+
+
+def measured_traffic(kernel_file: str, record: str):
+    """HBM bytes per launch from a rocprofv3 record, or None if the kernel changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", record)
+    src = os.path.join(ROOT, kernel_file)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes"] if rec.get("kernel_source_sha256") == digest else None
 
 
 def progress(msg: str):
@@ -279,7 +297,9 @@ def main():
         "peak": round(VALU_PEAK_TOPS, 3),
         "unit": "T VALU lane-ops/s",
         "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic("paper_2307_16652_amd/csrc/pairwise.hpp",
+                                    "pass2_cohesion__grid3d_n16384.traffic.json") if (n, args.workload) == (N, "grid3d")
+        else None,
         "kernel": "pass2_cohesion",
         "kernel_ms": round(p2_ms, 3),
         "launches_per_step": p2_launches,

@@ -65,34 +65,40 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(D: np.ndarray, workload: str = "grid3d", target_s: float = 12.0):
-    """Oracle throughput on the host cores for a bounded row sample of D."""
+def cpu_baseline(D: np.ndarray, workload: str = "grid3d", rows_wanted: int = 256):
+    """Oracle throughput on the host cores for a seeded sample of rows of D.
+
+    Returns the cpu_baseline record and (rows, U_rows, C_rows) for error checks."""
     import oracle
 
     n = D.shape[0]
     threads = oracle.default_threads()
     rng = np.random.default_rng(123)
-    probe_rows = max(threads, 4)
-    rows = rng.choice(n, size=probe_rows, replace=False)
+    k = min(n, rows_wanted)
+    rows = np.sort(rng.choice(n, size=k, replace=False))
     t0 = time.perf_counter()
-    oracle.pald_rows(D, rows, threads=threads)
-    t_probe = time.perf_counter() - t0
-    per_row = t_probe / probe_rows
-    k = int(max(probe_rows, min(n, (target_s / max(per_row, 1e-9)))))
-    k = max(threads, (k // threads) * threads)
-    rows = rng.choice(n, size=k, replace=False)
-    t0 = time.perf_counter()
-    oracle.pald_rows(D, rows, threads=threads)
+    Uo, Co = oracle.pald_rows(D, rows, threads=threads)
     t = time.perf_counter() - t0
     value = k * 2.0 * n * n / t / 1e9
-    return {
+    rec = {
         "value": round(value, 4),
         "unit": "G triplet comparisons/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{k} random rows of U and C of the n={n} {workload} matrix (2*n^2 terms per row), "
-                  f"{t:.1f} s wall",
+        "sample": f"{k} seeded random rows of U and C of the n={n} {workload} matrix "
+                  f"(2*n^2 terms per row), {t:.1f} s wall",
     }
+    return rec, (rows, Uo, Co)
+
+
+def error_stats(C_rows: np.ndarray, Co: np.ndarray) -> dict:
+    """Max / mean relative error of GPU cohesion rows against the oracle's."""
+    C_rows = C_rows.astype(np.float64)
+    nz = Co != 0
+    rel = np.abs(C_rows[nz] - Co[nz]) / np.abs(Co[nz])
+    return {"max_rel": float(rel.max()) if rel.size else 0.0,
+            "mean_rel": float(rel.mean()) if rel.size else 0.0,
+            "exact_zeros_ok": bool((C_rows[~nz] == 0).all())}
 
 
 def batched_bench(dev, reps: int = 3):
@@ -307,6 +313,7 @@ def main():
     kernels = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
 
     extra = {}
+    Cf = None
     if not args.no_comparators:
         progress("comparator: float64-accumulate pass 2")
         Cf = torch.empty_like(C)
@@ -324,22 +331,30 @@ def main():
             "f64_accumulate_pass2_ms": round(kf["pass2_cohesion"][0], 3),
             "compensated_vs_f64_max_rel": float(diff.max().item()),
         }
-        del Cf
     if not args.no_comparators:
         extra["variants_n4096"] = variants_bench(dev)
         progress(f"variants: {extra['variants_n4096']}")
     extra["pass1_focus_lane_ops_frac"] = round(p1_ops / (p1_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
+
+    base = None
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle rows)")
+        base, (rows, Uo, Co) = cpu_baseline(D if D is not None else Dg.cpu().numpy(), args.workload)
+        ridx = torch.from_numpy(rows).to(dev)
+        err = {"rows": int(rows.size),
+               "U_rows_equal": bool(np.array_equal(U[ridx].cpu().numpy(), Uo)),
+               "compensated": error_stats(C[ridx].cpu().numpy(), Co)}
+        if Cf is not None:
+            err["f64_accumulate"] = error_stats(Cf[ridx].cpu().numpy(), Co)
+        extra["error_vs_oracle"] = err
+        progress(f"error vs oracle: {err}")
+    del Cf
 
     if not args.no_batched:
         del U, C, ws
         torch.cuda.empty_cache()
         extra["batched"] = batched_bench(dev)
         progress(f"batched: {extra['batched']}")
-
-    base = None
-    if not args.no_cpu_baseline:
-        progress("cpu baseline (oracle rows)")
-        base = cpu_baseline(D if D is not None else Dg.cpu().numpy(), args.workload)
 
     out = {
         "metric": f"triplet comparisons/sec (G/s) + % VALU peak, n={n} fp32; batched matrices/sec",

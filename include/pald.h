@@ -34,11 +34,13 @@
  * - The hot calls allocate no device memory.  Batch plans own a small device
  *   descriptor allocated at plan creation.
  * - Comparisons are made on the float32 input values exactly as given, so U
- *   is exact.  C accumulates float32 weights 1/U in float32 runs of 8 terms
+ *   is exact.  C accumulates float32 weights 1/U in float32 runs of 12 terms
  *   folded into per-tile Kahan-compensated partials; float64 is used only for
  *   the final cross-tile reduction and the 1/(n-1) scaling.  Relative error
- *   of every C entry <= 11 * 2^-24 (6.6e-7); entries whose exact value is 0
- *   are exactly 0.  Results are deterministic for a fixed configuration.
+ *   of every C entry <= 15 * 2^-24 (8.9e-7); entries whose exact value is 0
+ *   are exactly 0.  Results of the pairwise and batched paths are
+ *   deterministic for a fixed configuration (the triplet variant's float64
+ *   atomics make its last bits order-dependent).
  */
 #ifndef PALD_H
 #define PALD_H

@@ -58,7 +58,10 @@ constexpr int BATCH_THREADS = PALD_BATCH_THREADS;
 // single-matrix pass-1 register tile would push the kernel to one wave per
 // SIMD.
 constexpr int BATCH_P1_T = 64, BATCH_P1_RX = BATCH_THREADS == 256 ? 2 : 1;
-constexpr int BATCH_P2_T = 64, BATCH_P2_RX = BATCH_THREADS == 256 ? 4 : 2, BATCH_P2_KY = 16;
+#ifndef PALD_P2_KY
+#define PALD_P2_KY 12
+#endif
+constexpr int BATCH_P2_T = 64, BATCH_P2_RX = BATCH_THREADS == 256 ? 4 : 2, BATCH_P2_KY = PALD_P2_KY;
 using BatchP1 = Pass1Cfg<BATCH_P1_T, BATCH_P1_RX, 8, 16>;
 using BatchP2 = Pass2Cfg<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY>;
 static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS,

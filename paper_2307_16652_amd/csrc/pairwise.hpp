@@ -23,8 +23,10 @@
 //    needed;
 //  * pass 1 uses the symmetry of U: only tiles with bx <= by run and they
 //    write their transpose too;
-//  * pass 2 accumulates float32 runs of 8 terms, folds each run into a Kahan
-//    (sum, compensation) pair, and reduces the pair in float64 at the end.
+//  * pass 2 accumulates float32 runs of 12 terms, folds each run into a Kahan
+//    (sum, compensation) pair, and reduces the pair in float64 at the end;
+//    the worst-case relative error is (12 + 3) * 2^-24 < 1e-6 (rounding of
+//    W, the run, the fold and the final store).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -419,6 +421,9 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // (s_and), so no vector select waits on a mask written by the vector
 // instruction just before it.
 
+#ifndef PALD_P2_RUN
+#define PALD_P2_RUN 12
+#endif
 template <int T, int RX, int KY>
 struct Pass2Cfg {
     static constexpr int RZ = 4;                        // z per thread (the term block's width)
@@ -430,7 +435,7 @@ struct Pass2Cfg {
     static constexpr int VEC_PER_CHUNK = KY * ROW / 4;
     static constexpr int VEC_PER_THREAD = VEC_PER_CHUNK / NT;
     static constexpr int LDS_VEC = 2 * KY * LDS_ROW / 4; // uint4 of LDS, double-buffered
-    static constexpr int RUN = 8;                       // float32 run length before a Kahan fold
+    static constexpr int RUN = PALD_P2_RUN;             // float32 run length before a Kahan fold
     static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(KY % RUN == 0, "KY must be a multiple of the run length");
     static_assert(T % 4 == 0, "tile side must be a multiple of 4");
@@ -531,48 +536,62 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) fetch(ybeg + (c + 1) * KY);
         const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (Cfg::LDS_VEC / 2));
-#pragma unroll 1
-        for (int y0 = 0; y0 < KY; y0 += Cfg::RUN) {
+        // operands of staged row yr: a = d_yx, W_yx, W_yx/2 over x; b = d_yz, W_yz, W_yz/2 over z
+        auto load_row = [&](int yr, uint32_t (&av)[RX], float (&wx)[RX], float (&whx)[RX], uint32_t (&bv)[RZ],
+                            float (&wz)[RZ], float (&whz)[RZ]) {
+            const uint32_t *row = s + yr * Cfg::LDS_ROW;
 #pragma unroll
-            for (int yy = 0; yy < Cfg::RUN; ++yy) {
-                const uint32_t *row = s + (y0 + yy) * Cfg::LDS_ROW;
+            for (int i = 0; i < RX; ++i) {
+                av[i] = row[tx * RX + i];
+                wx[i] = __uint_as_float(row[T + tx * RX + i]);
+                whx[i] = __uint_as_float(row[4 * T + tx * RX + i]);
+            }
+#pragma unroll
+            for (int j = 0; j < RZ; ++j) {
+                bv[j] = row[2 * T + tz * RZ + j];
+                wz[j] = __uint_as_float(row[3 * T + tz * RZ + j]);
+                whz[j] = __uint_as_float(row[5 * T + tz * RZ + j]);
+            }
+        };
+        if (F64) {
+            // reference form: plain float64 accumulation, no runs
+#pragma unroll 2
+            for (int yr = 0; yr < KY; ++yr) {
                 uint32_t av[RX], bv[RZ];
                 float wx[RX], whx[RX], wz[RZ], whz[RZ];
+                load_row(yr, av, wx, whx, bv, wz, whz);
 #pragma unroll
-                for (int i = 0; i < RX; ++i) {
-                    av[i] = row[tx * RX + i];
-                    wx[i] = __uint_as_float(row[T + tx * RX + i]);
-                    whx[i] = __uint_as_float(row[4 * T + tx * RX + i]);
-                }
+                for (int i = 0; i < RX; ++i)
 #pragma unroll
-                for (int j = 0; j < RZ; ++j) {
-                    bv[j] = row[2 * T + tz * RZ + j];
-                    wz[j] = __uint_as_float(row[3 * T + tz * RZ + j]);
-                    whz[j] = __uint_as_float(row[5 * T + tz * RZ + j]);
-                }
-                if (F64) {
-#pragma unroll
-                    for (int i = 0; i < RX; ++i)
-#pragma unroll
-                        for (int j = 0; j < RZ; ++j) {
-                            const uint32_t tt = t[i][j];
-                            const uint64_t in = lane_mask(tt <= av[i]) & lane_mask(tt <= bv[j]);
-                            float vf = lane_bit(in) ? whx[i] : 0.0f;
-                            vf = lane_bit(in & lane_mask(tt < bv[j])) ? wx[i] : vf;
-                            float vr = lane_bit(in) ? whz[j] : 0.0f;
-                            vr = lane_bit(in & lane_mask(tt < av[i])) ? wz[j] : vr;
-                            af[i][j] += (double)vf;
-                            ar[i][j] += (double)vr;
-                        }
-                } else if (yy == 0) {
-#pragma unroll
-                    for (int i = 0; i < RX; ++i) cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < RX; ++i) cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
-                }
+                    for (int j = 0; j < RZ; ++j) {
+                        const uint32_t tt = t[i][j];
+                        const uint64_t in = lane_mask(tt <= av[i]) & lane_mask(tt <= bv[j]);
+                        float vf = lane_bit(in) ? whx[i] : 0.0f;
+                        vf = lane_bit(in & lane_mask(tt < bv[j])) ? wx[i] : vf;
+                        float vr = lane_bit(in) ? whz[j] : 0.0f;
+                        vr = lane_bit(in & lane_mask(tt < av[i])) ? wz[j] : vr;
+                        af[i][j] += (double)vf;
+                        ar[i][j] += (double)vr;
+                    }
             }
-            if (!F64) {
+        } else {
+#pragma unroll 1
+            for (int y0 = 0; y0 < KY; y0 += Cfg::RUN) {
+#pragma unroll
+                for (int yy = 0; yy < Cfg::RUN; ++yy) {
+                    uint32_t av[RX], bv[RZ];
+                    float wx[RX], whx[RX], wz[RZ], whz[RZ];
+                    load_row(y0 + yy, av, wx, whx, bv, wz, whz);
+                    if (yy == 0) {
+#pragma unroll
+                        for (int i = 0; i < RX; ++i)
+                            cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < RX; ++i)
+                            cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                    }
+                }
                 // Kahan fold of the finished runs: sum - comp tracks the exact total.
 #pragma unroll
                 for (int i = 0; i < RX; ++i)

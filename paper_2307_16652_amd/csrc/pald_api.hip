@@ -29,7 +29,10 @@ using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
 #ifndef PALD_P2_RX
 #define PALD_P2_RX 4
 #endif
-constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = 16;
+#ifndef PALD_P2_KY
+#define PALD_P2_KY 12
+#endif
+constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = PALD_P2_KY;
 using P2 = Pass2Cfg<P2_T, P2_RX, P2_KY>;
 
 constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part

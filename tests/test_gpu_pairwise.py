@@ -241,3 +241,15 @@ def test_config_grid3d_n16384_sampled():
     U, C, err = parity(D, "grid3d n=16384 (26 oracle rows)", rows=rows)
     check_invariants(U, C, "grid3d")
     log(f"  max rel err {err:.3e}")
+
+
+def test_diagonal_identity_without_coincident_points():
+    """With no zero off-diagonal distance, every focus of x contains x with full
+    support, so C_xx = 1/(n-1) sum_{y != x} 1/U_xy (computed here from the GPU's U)."""
+    D = synth.mixture8d(n=400, seed=31)
+    assert (D[~np.eye(400, dtype=bool)] > 0).all()
+    U, C = gpu_cohesion(D)
+    Ud = U.astype(np.float64)
+    np.fill_diagonal(Ud, np.inf)
+    expect = (1.0 / Ud).sum(axis=1) / (400 - 1)
+    np.testing.assert_allclose(np.diag(C).astype(np.float64), expect, rtol=1e-6, atol=0)

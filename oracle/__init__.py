@@ -12,6 +12,16 @@ with it.
 
 with s(p, q) = [p < q] + 1/2 [p == q] (ties split, Section 5), in double
 precision after promoting the FP32 distances exactly to double.
+
+The steps around the two passes:
+
+* `local_depths` -- l_x = sum_z c_xz (Section 2: cohesion partitions the
+  local depth of Eq. (LD));
+* `strong_ties` -- the directed graph of the entries of C above a threshold,
+  in CSR form (Section 2 and Section 6 read community structure off the
+  cohesion matrix by thresholding it);
+* `distances` (`distance_oracle.c`) -- Euclidean or squared Euclidean
+  distances between points, the input Section 6 feeds to PaLD.
 """
 from __future__ import annotations
 
@@ -22,19 +32,20 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "pald_oracle.c")
+_SRCS = [os.path.join(_HERE, "pald_oracle.c"), os.path.join(_HERE, "distance_oracle.c")]
 _LIB = os.path.join(_HERE, "libpald_oracle.so")
 
 # Plain -O2: no -ffast-math / -Ofast, which would enable flush-to-zero and
-# change the outcome of comparisons between denormal distances.
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra"]
+# change the outcome of comparisons between denormal distances; no implicit
+# contraction of a multiply and an add into one fused operation either.
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra", "-ffp-contract=off"]
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into oracle/libpald_oracle.so."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -53,6 +64,8 @@ def _load():
         lib.pald_oracle_rows.restype = ctypes.c_int
         lib.pald_oracle_full.argtypes = [vp, i64, i64, vp, vp, ctypes.c_int]
         lib.pald_oracle_full.restype = ctypes.c_int
+        lib.pald_oracle_distances.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64]
+        lib.pald_oracle_distances.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -101,3 +114,62 @@ def pald(D, threads: int | None = None):
     if rc != 0:
         raise RuntimeError("pald_oracle_full failed (bad arguments)")
     return U, C
+
+
+def local_depths(C) -> np.ndarray:
+    """l_x = sum_z c_xz for every row x of C, in float64 (Section 2: cohesion
+    is partitioned local depth)."""
+    return np.asarray(C, dtype=np.float64).sum(axis=1)
+
+
+def strong_ties(C, threshold):
+    """The entries of a float32 cohesion matrix above `threshold`, as CSR.
+
+    Row x lists, in increasing order, every z != x with C[x][z] > threshold,
+    the comparison made in float32 (threshold rounded to float32 first).
+    Returns (row_ptr int64 [n+1], col int32 [nnz], val float32 [nnz]).
+    """
+    C = np.asarray(C)
+    if C.dtype != np.float32 or C.ndim != 2 or C.shape[0] != C.shape[1]:
+        raise ValueError("C must be a square float32 matrix")
+    t = np.float32(threshold)
+    n = C.shape[0]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for x in range(n):
+        z = np.nonzero(C[x] > t)[0]
+        z = z[z != x]
+        cols.append(z.astype(np.int32))
+        vals.append(C[x, z])
+        row_ptr[x + 1] = row_ptr[x] + z.size
+    col = np.concatenate(cols) if cols else np.zeros(0, np.int32)
+    val = np.concatenate(vals) if vals else np.zeros(0, np.float32)
+    return row_ptr, col.astype(np.int32), val.astype(np.float32)
+
+
+METRICS = {"euclidean": 0, "sqeuclidean": 1}
+
+
+def distances(P, metric: str = "euclidean", rows=None) -> np.ndarray:
+    """Distance matrix (or rows `rows` of it) of the points P [n, dim]
+    (float32 or float64) as float32, by the definition in distance_oracle.c."""
+    P = np.asarray(P)
+    if P.dtype not in (np.float32, np.float64):
+        P = P.astype(np.float64)
+    P = np.ascontiguousarray(P)
+    if P.ndim != 2:
+        raise ValueError("P must be [n, dim]")
+    n, dim = P.shape
+    dtype = 1 if P.dtype == np.float64 else 0
+    if rows is None:
+        out = np.empty((n, n), dtype=np.float32)
+        rp, nr = None, n
+    else:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
+        out = np.empty((rows.size, n), dtype=np.float32)
+        rp, nr = rows.ctypes.data, rows.size
+    rc = _load().pald_oracle_distances(P.ctypes.data, dtype, n, dim, dim, METRICS[metric], rp, nr,
+                                       out.ctypes.data, n)
+    if rc != 0:
+        raise RuntimeError("pald_oracle_distances failed (bad arguments)")
+    return out

@@ -1,0 +1,207 @@
+"""Pins of the oracle's steps around the two passes: local depths, the
+strong-tie export and the distance front end (CPU only).
+
+* local depths l_x = sum_z c_xz (Section 2: cohesion partitions the local
+  depth): the worked examples, the regular simplex and separated clusters in
+  closed form, Eq. (LD) evaluated as a probability by exact enumeration on
+  tiny inputs, and sum_x l_x = n/2;
+* strong ties (entries of C above a threshold, CSR): a pure-Python set
+  comprehension on random matrices, the extreme thresholds, entries equal to
+  the threshold, the diagonal, the two-cluster example;
+* distances: integer coordinates against exact integer arithmetic, scaled
+  Pythagorean triples, scipy's cdist, symmetry and zero diagonal.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import exact_pald
+import oracle
+import pins
+
+# ---------------------------------------------------------------------------
+# local depths
+
+# l_x of each worked example, by hand from its C (row sums)
+GOLDEN_DEPTHS = {
+    "example_i_two_points.txt": [Fraction(1, 2)] * 2,
+    "example_ii_line.txt": [Fraction(7, 12), Fraction(7, 12), Fraction(1, 3)],
+    "example_iii_equilateral.txt": [Fraction(1, 2)] * 3,
+    "example_iv_two_clusters.txt": [Fraction(1, 2)] * 4,
+    "example_v_duplicates.txt": [Fraction(7, 12), Fraction(7, 12), Fraction(1, 3)],
+}
+
+
+def test_depths_of_the_worked_examples():
+    files = {f.rsplit("/", 1)[-1]: f for f in pins.golden_files()}
+    assert set(files) == set(GOLDEN_DEPTHS)
+    for name, expect in GOLDEN_DEPTHS.items():
+        D, _, _ = pins.load_golden(files[name])
+        _, C = oracle.pald(D, threads=1)
+        got = oracle.local_depths(C)
+        np.testing.assert_allclose(got, [float(v) for v in expect], rtol=1e-14, atol=0, err_msg=name)
+
+
+def depth_by_probability(D):
+    """Eq. (LD): l_x = Pr[d_Zx < d_ZY], Y uniform on S minus x, Z uniform on the
+    local focus of (x, Y), a tie counting one half -- exact rationals."""
+    d = [[Fraction(float(v)) for v in row] for row in D]
+    n = len(d)
+    out = []
+    for x in range(n):
+        p = Fraction(0)
+        for Y in range(n):
+            if Y == x:
+                continue
+            F = exact_pald.focus(d, x, Y)
+            for Z in F:
+                p += Fraction(1, n - 1) * Fraction(1, len(F)) * exact_pald.support(d[Z][x], d[Z][Y])
+        out.append(p)
+    return out
+
+
+def test_depths_equal_the_probability_definition():
+    rng = np.random.default_rng(11)
+    for k in range(12):
+        n = int(rng.integers(2, 8))
+        if k % 2:
+            A = rng.integers(0, 4, size=(n, n)).astype(np.float32)  # heavy ties, duplicates
+        else:
+            A = rng.uniform(0.0, 1.0, size=(n, n)).astype(np.float32)
+        D = np.triu(A, 1)
+        D = (D + D.T).astype(np.float32)
+        _, C = oracle.pald(D, threads=1)
+        got = oracle.local_depths(C)
+        exact = depth_by_probability(D)
+        for x in range(n):
+            assert abs(got[x] - float(exact[x])) <= 1e-14 * max(1.0, float(exact[x])), (k, x)
+
+
+def test_depths_closed_forms():
+    # regular simplex: l_x = 1/n + (n-1)(n-2)/(2n(n-1)) = 1/2
+    for n in (2, 3, 7, 16):
+        D = np.full((n, n), 2.0, dtype=np.float32)
+        np.fill_diagonal(D, 0)
+        _, C = oracle.pald(D, threads=1)
+        np.testing.assert_allclose(oracle.local_depths(C), 0.5, rtol=1e-14, atol=0)
+    # separated clusters: l_x = C_xx + (a-1) C_same + sum over other clusters c * C_cross
+    sizes = (2, 5, 1, 3)
+    D, lab = pins.separated_clusters(sizes, (0.25, 3.0, 1.0, 2.5), 10.0)
+    n = D.shape[0]
+    _, C = oracle.pald(D, threads=1)
+    got = oracle.local_depths(C)
+    for x in range(n):
+        a = sizes[lab[x]]
+        v = (Fraction(a - 1, a) + Fraction(n - a, n)) / (n - 1)
+        v += (a - 1) * (Fraction(a - 2, 2 * a) + Fraction(n - a, n)) / (n - 1)
+        for k, c in enumerate(sizes):
+            if k != lab[x]:
+                v += c * Fraction(n - a - c, 2 * n * (n - 1))
+        assert abs(got[x] - float(v)) <= 1e-14, (x, got[x], v)
+
+
+def test_depths_sum_to_half_n():
+    rng = np.random.default_rng(3)
+    for n in (5, 40, 97):
+        P = rng.normal(size=(n, 3))
+        D = oracle.distances(P)
+        _, C = oracle.pald(D)
+        depth = oracle.local_depths(C)
+        assert abs(depth.sum() - n / 2) <= 1e-12 * n
+        assert (depth >= 0).all() and (depth <= 1 + 1e-12).all()
+
+
+# ---------------------------------------------------------------------------
+# strong ties
+
+
+def ties_by_sets(C, t):
+    t = np.float32(t)
+    n = C.shape[0]
+    return [sorted(z for z in range(n) if z != x and C[x, z] > t) for x in range(n)]
+
+
+def csr_rows(row_ptr, col):
+    return [list(col[row_ptr[x]:row_ptr[x + 1]]) for x in range(len(row_ptr) - 1)]
+
+
+def test_strong_ties_brute_force():
+    rng = np.random.default_rng(5)
+    for n in (1, 2, 3, 9, 33):
+        C = rng.uniform(0, 1, size=(n, n)).astype(np.float32)
+        for t in (0.0, 0.25, 0.5, 0.9, 1.0):
+            rp, col, val = oracle.strong_ties(C, t)
+            assert rp[0] == 0 and rp[-1] == col.size == val.size
+            assert csr_rows(rp, col) == ties_by_sets(C, t)
+            rows = np.repeat(np.arange(n), np.diff(rp))
+            assert np.array_equal(val, C[rows, col])
+
+
+def test_strong_ties_extremes_equality_and_diagonal():
+    n = 6
+    C = np.full((n, n), 0.25, dtype=np.float32)
+    np.fill_diagonal(C, 0.9)  # the diagonal is never an edge
+    rp, col, _ = oracle.strong_ties(C, 0.1)
+    assert csr_rows(rp, col) == [[z for z in range(n) if z != x] for x in range(n)]
+    rp, col, _ = oracle.strong_ties(C, 0.25)  # equal to the threshold: not above it
+    assert rp[-1] == 0
+    rp, col, _ = oracle.strong_ties(C, 1.0)
+    assert rp[-1] == 0
+    C[2, 4] = np.nextafter(np.float32(0.25), np.float32(1))
+    rp, col, _ = oracle.strong_ties(C, 0.25)
+    assert csr_rows(rp, col) == [[], [], [4], [], [], []]
+
+
+def test_strong_ties_of_two_clusters():
+    files = {f.rsplit("/", 1)[-1]: f for f in pins.golden_files()}
+    D, _, _ = pins.load_golden(files["example_iv_two_clusters.txt"])
+    _, C = oracle.pald(D, threads=1)  # within-cluster 1/6, across 0, diagonal 1/3
+    rp, col, _ = oracle.strong_ties(C.astype(np.float32), 0.1)
+    assert csr_rows(rp, col) == [[1], [0], [3], [2]]
+
+
+# ---------------------------------------------------------------------------
+# distances
+
+
+def test_distances_integer_coordinates_exact():
+    rng = np.random.default_rng(2)
+    for dim in (1, 3, 16):
+        P = rng.integers(-40, 41, size=(30, dim))
+        exact = np.array([[sum(int(a - b) ** 2 for a, b in zip(p, q)) for q in P] for p in P])
+        for dt in (np.float32, np.float64):
+            D = oracle.distances(P.astype(dt), "sqeuclidean")
+            assert np.array_equal(D, exact.astype(np.float32))
+            E = oracle.distances(P.astype(dt), "euclidean")
+            assert np.array_equal(E, np.sqrt(exact.astype(np.float64)).astype(np.float32))
+
+
+def test_distances_pythagorean():
+    P = np.array([[0, 0, 0], [3, 4, 0], [0, 5, 12], [8, 15, 0], [-3, -4, 0]], dtype=np.float32) * 0.5
+    D = oracle.distances(P)
+    assert D[0, 1] == 2.5 and D[0, 2] == 6.5 and D[0, 3] == 8.5 and D[1, 4] == 5.0
+
+
+def test_distances_match_scipy_and_are_symmetric():
+    from scipy.spatial.distance import cdist
+
+    rng = np.random.default_rng(8)
+    for dt, dim in ((np.float32, 8), (np.float64, 16), (np.float64, 300)):
+        P = rng.normal(size=(60, dim)).astype(dt)
+        for metric in ("euclidean", "sqeuclidean"):
+            D = oracle.distances(P, metric)
+            ref = cdist(P.astype(np.float64), P.astype(np.float64), metric).astype(np.float32)
+            ulp = np.abs(D.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64))
+            assert ulp.max() <= 1 and (ulp == 0).mean() > 0.99, (dt, dim, metric)
+            assert np.array_equal(D, D.T) and (np.diag(D) == 0).all()
+            assert np.array_equal(oracle.distances(P, metric, rows=[5, 0, 59]), D[[5, 0, 59]])
+
+
+def test_distances_bad_arguments():
+    with pytest.raises(KeyError):
+        oracle.distances(np.zeros((3, 2)), "manhattan")
+    with pytest.raises(RuntimeError):
+        oracle.distances(np.zeros((3, 2)), rows=[3])

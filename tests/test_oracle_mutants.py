@@ -68,3 +68,77 @@ def test_mutant_is_caught(name, tmp_path):
         except AssertionError:
             caught.append(pin.__name__)
     assert caught, f"mutant {name} passed every pin"
+
+
+# ---------------------------------------------------------------------------
+# the distance front end and the steps after the two passes
+
+DIST_SRC = os.path.join(ROOT, "oracle", "distance_oracle.c")
+DIST_MUTANTS = {
+    "dim_off_by_one": ("k < dim;", "k < dim - 1;"),
+    "no_sqrt": ("sqrt(acc) : acc", "acc : acc"),
+    "metric_swapped": ("metric == ORACLE_METRIC_EUCLIDEAN ?", "metric == ORACLE_METRIC_SQEUCLIDEAN ?"),
+    "same_point_twice": ("- coord(P, dtype, ldp, y, k)", "- coord(P, dtype, ldp, x, k)"),
+    "f64_read_as_f32": ("if (dtype == ORACLE_F64)", "if (0)"),
+    "abs_not_square": ("acc = fma(delta, delta, acc);", "acc = acc + fabs(delta);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DIST_MUTANTS))
+def test_distance_mutant_is_caught(name, tmp_path, monkeypatch):
+    import oracle
+    import test_oracle_analysis as ta
+
+    src = open(DIST_SRC).read()
+    old, new = DIST_MUTANTS[name]
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-o", str(so), str(c), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    lib.pald_oracle_distances.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64]
+    lib.pald_oracle_distances.restype = ctypes.c_int
+    monkeypatch.setattr(oracle, "_lib", lib)
+    caught = []
+    for pin in (ta.test_distances_integer_coordinates_exact, ta.test_distances_pythagorean,
+                ta.test_distances_match_scipy_and_are_symmetric):
+        try:
+            pin()
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"distance mutant {name} passed every pin"
+
+
+PY_MUTANTS = {
+    "ties_at_equality": ("strong_ties", "C[x] > t", "C[x] >= t"),
+    "ties_keep_diagonal": ("strong_ties", "z = z[z != x]", "z = z"),
+    "depth_column_sums": ("local_depths", ".sum(axis=1)", ".sum(axis=0)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_step_mutant_is_caught(name, monkeypatch):
+    import inspect
+    import textwrap
+
+    import oracle
+    import test_oracle_analysis as ta
+
+    fn, old, new = PY_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, fn)))
+    assert src.count(old) == 1, f"mutation anchor for {name} not found"
+    scope = dict(vars(oracle))
+    exec(src.replace(old, new), scope)
+    monkeypatch.setattr(oracle, fn, scope[fn])
+    caught = []
+    for pin in (ta.test_depths_of_the_worked_examples, ta.test_depths_equal_the_probability_definition,
+                ta.test_depths_closed_forms, ta.test_strong_ties_brute_force,
+                ta.test_strong_ties_extremes_equality_and_diagonal, ta.test_strong_ties_of_two_clusters):
+        try:
+            pin()
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"mutant {name} passed every pin"

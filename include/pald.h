@@ -139,6 +139,67 @@ pald_status pald_check_input(const float *D, int64_t n, int64_t ldd,
                              void *ws, size_t ws_bytes, void *stream,
                              uint32_t *flags_out);
 
+/* ---------------------------------------------------------------------------
+ * Before and after the two passes.
+ * ------------------------------------------------------------------------- */
+
+/* Coordinate types and metrics of the distance front end. */
+enum { PALD_DTYPE_F32 = 0, PALD_DTYPE_F64 = 1 };
+enum { PALD_METRIC_EUCLIDEAN = 0, PALD_METRIC_SQEUCLIDEAN = 1 };
+
+/*
+ * Distance front end: the n x n distance matrix of n points in R^dim, the
+ * input PaLD takes (Section 6 applies it to Euclidean distances between
+ * word-embedding vectors).  Every entry is, in float64 with round-to-nearest,
+ *   acc = 0;  for k = 0 .. dim-1 in order: delta = p_xk - p_yk,
+ *                                           acc = fma(delta, delta, acc)
+ *   D[x][y] = (float)acc               PALD_METRIC_SQEUCLIDEAN
+ *   D[x][y] = (float)sqrt(acc)         PALD_METRIC_EUCLIDEAN
+ * so D is exactly symmetric with a zero diagonal and meets the input
+ * contract whenever the coordinates are finite.
+ *   P   [n x ldp]  coordinates, device, float32 or float64 (dtype), read only
+ *   D   [n x ldd]  float32 output, device; every entry of the n x n block written
+ *   flags          0 or PALD_FLAG_TIMING (kind 8)
+ * Errors: PALD_ERR_ARG for null P/D, n < 1, dim < 1, ldp < dim, ldd < n;
+ * PALD_ERR_UNSUPPORTED for an unknown dtype, metric or flag.
+ */
+pald_status pald_distances(const void *P, int32_t dtype, int64_t n, int64_t dim, int64_t ldp,
+                           int32_t metric, float *D, int64_t ldd, void *stream, uint32_t flags);
+
+/*
+ * Local depths (Section 2: cohesion partitions the local depth of Eq. (LD),
+ * l_x = sum_z c_xz): depth[x] = (float)(sum_z C[x][z]), summed in float64 in
+ * a fixed order.  With C from pald_cohesion the relative error of each depth
+ * is below 1e-6 and the depths sum to n/2.
+ *   C      [n x ldc]  float32, device, read only
+ *   depth  [n]        float32 output, device
+ *   flags             0 or PALD_FLAG_TIMING (kind 9)
+ * Errors: PALD_ERR_ARG for null pointers, n < 1, ldc < n;
+ * PALD_ERR_UNSUPPORTED for an unknown flag.
+ */
+pald_status pald_local_depths(const float *C, int64_t n, int64_t ldc, float *depth, void *stream,
+                              uint32_t flags);
+
+/*
+ * Strong-tie graph (Sections 2 and 6 read community structure off C by a
+ * threshold; the threshold itself is the caller's): the directed edges
+ * x -> z, z != x, with C[x][z] > threshold (compared in float32), in CSR
+ * form with the columns of each row increasing:
+ *   row_ptr [n + 1]  int64 output, device: row_ptr[0] = 0, row x's edges are
+ *                    positions row_ptr[x] .. row_ptr[x+1]-1; always written
+ *   col     [cap]    int32 output, device: the z of each edge
+ *   val     [cap]    float32 output, device, or NULL: C[x][z] of each edge
+ * Only positions < cap are written; row_ptr[n] is the edge count, so a
+ * caller that does not know it calls once with cap = 0 (col may then be
+ * NULL), reads row_ptr[n] after synchronising, and calls again.
+ * flags: 0 or PALD_FLAG_TIMING (kinds 10 and 11).
+ * Errors: PALD_ERR_ARG for null C/row_ptr, null col with cap > 0, n < 1,
+ * ldc < n, cap < 0, a NaN threshold; PALD_ERR_UNSUPPORTED for n > 2^31-1 or
+ * an unknown flag.
+ */
+pald_status pald_strong_ties(const float *C, int64_t n, int64_t ldc, float threshold, int64_t *row_ptr,
+                             int32_t *col, float *val, int64_t cap, void *stream, uint32_t flags);
+
 /*
  * Batched mode: many independent matrices of different sizes in one
  * persistent launch (no batching in the paper; a GPU-side extension).
@@ -256,7 +317,8 @@ void pald_batch_graph_destroy(pald_batch_graph *graph);
  * for k < kinds, and forgets the records.  Kinds: 0 pass-1 focus sizes,
  * 1 weight preparation, 2 pass-2 cohesion, 3 cross-chunk finalize,
  * 4 batched persistent kernel, 5 triplet pass 1, 6 triplet pass 2,
- * 7 triplet finalize.  Returns the number of kinds defined (8).
+ * 7 triplet finalize, 8 distances, 9 local depths, 10 strong-tie count and
+ * scan, 11 strong-tie fill.  Returns the number of kinds defined (12).
  */
 int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds);
 

@@ -40,7 +40,7 @@ def hipcc() -> str:
 
 
 def sources():
-    return [os.path.join(CSRC, "pald_api.hip")]
+    return [os.path.join(CSRC, f) for f in ("pald_api.hip", "frontend_api.hip")]
 
 
 def build(verbose: bool = False) -> str:

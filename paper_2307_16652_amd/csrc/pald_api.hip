@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "pald.h"
+#include "host_common.hpp"
 #include "pairwise.hpp"
 #include "batched.hpp"
 #include "triplet.hpp"
@@ -19,6 +20,7 @@
 namespace {
 
 using namespace pald;
+using namespace pald_host;
 
 // ---- single-matrix tile configuration -------------------------------------
 // pass 1: 128 x 128 (x,y) tiles, 8 x 8 counters per thread, 16 z rows per stage
@@ -41,41 +43,6 @@ constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
 constexpr int64_t P1_TILES_PER_LAUNCH = 32768;
 constexpr int64_t P2_TILES_PER_LAUNCH = 65536;
 constexpr int64_t TRI_TILES_PER_LAUNCH = 8192;
-constexpr size_t ALIGN = 256;
-
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// ---- timing records -------------------------------------------------------
-constexpr int NUM_KINDS = 8;
-struct TimingRec {
-    int kind;
-    hipEvent_t start, stop;
-};
-std::mutex g_timing_mu;
-std::vector<TimingRec> g_timing;
-
-struct ScopedTiming {
-    bool on;
-    int kind;
-    hipStream_t s;
-    hipEvent_t a = nullptr, b = nullptr;
-    ScopedTiming(bool on_, int kind_, hipStream_t s_) : on(on_), kind(kind_), s(s_) {
-        if (on) {
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-                on = false;
-                return;
-            }
-            (void)hipEventRecord(a, s);
-        }
-    }
-    ~ScopedTiming() {
-        if (!on) return;
-        (void)hipEventRecord(b, s);
-        std::lock_guard<std::mutex> g(g_timing_mu);
-        g_timing.push_back({kind, a, b});
-    }
-};
 
 // ---- options -----------------------------------------------------------------
 struct Opts {
@@ -154,16 +121,6 @@ pald_status make_plan(int64_t n, const Opts &o, Plan &p) {
     if (p.y_chunks > 1) off = align_up(off + (size_t)p.y_chunks * (size_t)n * (size_t)n * sizeof(double), ALIGN);
     p.bytes = std::max<size_t>(off, ALIGN);
     return PALD_OK;
-}
-
-// rows of an elementwise n x n kernel are grid-strided over gridDim.y <= 65535
-inline unsigned rows_grid(int64_t n) { return (unsigned)std::min<int64_t>(n, 65535); }
-
-inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-
-pald_status launch_status() {
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? PALD_OK : PALD_ERR_DEVICE;
 }
 
 // Pass 1 into (U, W); W may be null.  Returns after enqueueing.
@@ -384,8 +341,8 @@ pald_status pald_check_input(const float *D, int64_t n, int64_t ldd, void *ws, s
 int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds) {
     std::vector<TimingRec> recs;
     {
-        std::lock_guard<std::mutex> g(g_timing_mu);
-        recs.swap(g_timing);
+        std::lock_guard<std::mutex> g(timing_mutex());
+        recs.swap(timing_records());
     }
     for (int32_t k = 0; k < kinds && k < NUM_KINDS; ++k) {
         if (total_ms) total_ms[k] = 0.0;

@@ -21,7 +21,10 @@ VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2}
 ACCUMS = {"compensated": 0, "f64": 1}
 FLAG_TIMING = 1
 TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
-                "triplet_pass1", "triplet_pass2", "triplet_finalize")
+                "triplet_pass1", "triplet_pass2", "triplet_finalize", "distances", "local_depths",
+                "strong_ties_count", "strong_ties_fill")
+DTYPES = {"float32": 0, "float64": 1}
+METRICS = {"euclidean": 0, "sqeuclidean": 1}
 INPUT_FLAGS = {1: "nan", 2: "inf", 4: "negative", 8: "asymmetric", 16: "nonzero_diagonal"}
 
 #: every symbol include/pald.h declares
@@ -31,7 +34,7 @@ EXPORTED = (
     "pald_batch_total_elements", "pald_batch_offset", "pald_batch_grid", "pald_cohesion_batched",
     "pald_batch_timestamps", "pald_batch_queue", "pald_batch_plan_destroy",
     "pald_batch_graph_create", "pald_batch_graph_launch", "pald_batch_graph_destroy",
-    "pald_timings_collect",
+    "pald_timings_collect", "pald_distances", "pald_local_depths", "pald_strong_ties",
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
@@ -158,6 +161,13 @@ def load_library(path: str | None = None):
     lib.pald_batch_graph_destroy.restype = None
     lib.pald_timings_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]
     lib.pald_timings_collect.restype = i32
+    u32 = ctypes.c_uint32
+    lib.pald_distances.argtypes = [vp, i32, i64, i64, i64, i32, vp, i64, vp, u32]
+    lib.pald_distances.restype = i32
+    lib.pald_local_depths.argtypes = [vp, i64, i64, vp, vp, u32]
+    lib.pald_local_depths.restype = i32
+    lib.pald_strong_ties.argtypes = [vp, i64, i64, ctypes.c_float, vp, vp, vp, i64, vp, u32]
+    lib.pald_strong_ties.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -271,6 +281,56 @@ def check_input(D) -> list[str]:
     if st not in (OK, ERR_INPUT):
         _check(st, "pald_check_input")
     return [name for bit, name in INPUT_FLAGS.items() if flags.value & bit]
+
+
+def distances(P, metric: str = "euclidean", *, timing: bool = False, out=None):
+    """D (float32, n x n) from points P [n, dim] (float32 or float64 torch tensor on the GPU)."""
+    torch = _torch()
+    if not isinstance(P, torch.Tensor) or not P.is_cuda or P.dim() != 2:
+        raise TypeError("P must be a 2-D torch tensor on a HIP (cuda) device")
+    if P.dtype not in (torch.float32, torch.float64):
+        raise ValueError("P must be float32 or float64")
+    if P.stride(1) != 1:
+        raise ValueError("P must be row-major with unit column stride")
+    n, dim = P.shape
+    D = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=P.device)
+    st = load_library().pald_distances(
+        P.data_ptr(), DTYPES["float64" if P.dtype == torch.float64 else "float32"], n, dim,
+        max(P.stride(0), dim), METRICS[metric], D.data_ptr(), D.stride(0), _stream_ptr(P.device),
+        FLAG_TIMING if timing else 0)
+    _check(st, "pald_distances")
+    return D
+
+
+def local_depths(C, *, timing: bool = False, out=None):
+    """Local depths l_x = sum_z C[x][z] (float32 [n]) of a cohesion matrix on the GPU."""
+    torch = _torch()
+    n, ldc = _check_matrix(C)
+    depth = out if out is not None else torch.empty(n, dtype=torch.float32, device=C.device)
+    st = load_library().pald_local_depths(C.data_ptr(), n, ldc, depth.data_ptr(), _stream_ptr(C.device),
+                                          FLAG_TIMING if timing else 0)
+    _check(st, "pald_local_depths")
+    return depth
+
+
+def strong_ties(C, threshold: float, *, with_values: bool = True, timing: bool = False):
+    """CSR (row_ptr int64 [n+1], col int32 [nnz], val float32 [nnz] or None) of the
+    entries C[x][z] > threshold, z != x.  Two library calls: count, then fill."""
+    torch = _torch()
+    n, ldc = _check_matrix(C)
+    lib = load_library()
+    flags = FLAG_TIMING if timing else 0
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=C.device)
+    st = lib.pald_strong_ties(C.data_ptr(), n, ldc, float(threshold), row_ptr.data_ptr(), None, None, 0,
+                              _stream_ptr(C.device), flags)
+    _check(st, "pald_strong_ties")
+    nnz = int(row_ptr[n].item())
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=C.device)
+    val = torch.empty(max(nnz, 1), dtype=torch.float32, device=C.device) if with_values else None
+    st = lib.pald_strong_ties(C.data_ptr(), n, ldc, float(threshold), row_ptr.data_ptr(), col.data_ptr(),
+                              val.data_ptr() if val is not None else None, nnz, _stream_ptr(C.device), flags)
+    _check(st, "pald_strong_ties")
+    return row_ptr, col[:nnz], (val[:nnz] if val is not None else None)
 
 
 def timings_collect() -> dict:

@@ -102,7 +102,37 @@ def test_focus_sizes_and_check_input_bad_args():
 
 def test_timings_collect_without_records():
     lib = pald.load_library()
-    tot = (ctypes.c_double * 8)()
-    cnt = (ctypes.c_int64 * 8)()
-    assert lib.pald_timings_collect(tot, cnt, 8) == 8
-    assert list(cnt) == [0] * 8
+    k = len(pald.TIMING_KINDS)
+    tot = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    assert lib.pald_timings_collect(tot, cnt, k) == k == 12
+    assert list(cnt) == [0] * k
+
+
+def test_front_end_and_analysis_argument_errors():
+    lib = pald.load_library()
+    f = ctypes.c_void_p(0x10000)
+    # distances: P, dtype, n, dim, ldp, metric, D, ldd, stream, flags
+    assert lib.pald_distances(None, 0, 8, 3, 3, 0, f, 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 0, 8, 3, 3, 0, None, 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 0, 0, 3, 3, 0, f, 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 0, 8, 0, 3, 0, f, 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 0, 8, 3, 2, 0, f, 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 0, 8, 3, 3, 0, f, 7, None, 0) == pald.ERR_ARG
+    assert lib.pald_distances(f, 2, 8, 3, 3, 0, f, 8, None, 0) == pald.ERR_UNSUPPORTED
+    assert lib.pald_distances(f, 0, 8, 3, 3, 2, f, 8, None, 0) == pald.ERR_UNSUPPORTED
+    assert lib.pald_distances(f, 0, 8, 3, 3, 0, f, 8, None, 2) == pald.ERR_UNSUPPORTED
+    # local depths: C, n, ldc, depth, stream, flags
+    assert lib.pald_local_depths(None, 8, 8, f, None, 0) == pald.ERR_ARG
+    assert lib.pald_local_depths(f, 8, 8, None, None, 0) == pald.ERR_ARG
+    assert lib.pald_local_depths(f, 8, 7, f, None, 0) == pald.ERR_ARG
+    assert lib.pald_local_depths(f, 0, 8, f, None, 0) == pald.ERR_ARG
+    assert lib.pald_local_depths(f, 8, 8, f, None, 4) == pald.ERR_UNSUPPORTED
+    # strong ties: C, n, ldc, threshold, row_ptr, col, val, cap, stream, flags
+    assert lib.pald_strong_ties(None, 8, 8, 0.5, f, f, None, 4, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 8, 0.5, None, f, None, 4, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 8, 0.5, f, None, None, 4, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 8, 0.5, f, f, None, -1, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 7, 0.5, f, f, None, 4, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 8, float("nan"), f, f, None, 4, None, 0) == pald.ERR_ARG
+    assert lib.pald_strong_ties(f, 8, 8, 0.5, f, f, None, 4, None, 8) == pald.ERR_UNSUPPORTED

@@ -178,7 +178,8 @@ def batched_bench(dev, reps: int = 3):
 
 
 def variants_bench(dev, reps: int = 3):
-    """Pairwise vs triplet variant on the n = 4096 six-cluster mixture in R^8."""
+    """Pairwise vs hybrid (triplet pass 1 + pairwise pass 2) vs triplet variant on
+    the n = 4096 six-cluster mixture in R^8."""
     import torch
 
     from paper_2307_16652_amd import pald, synth
@@ -187,7 +188,7 @@ def variants_bench(dev, reps: int = 3):
     Dg = torch.from_numpy(synth.mixture8d(n=n)).to(dev)
     out = {"workload": "mixture8d n=4096 seed 2"}
     ref = None
-    for variant in ("pairwise", "triplet"):
+    for variant in ("pairwise", "hybrid", "triplet"):
         ws = pald.workspace(n, dev, variant=variant)
         U, C = pald.cohesion(Dg, variant=variant, ws=ws)
         torch.cuda.synchronize()
@@ -203,12 +204,71 @@ def variants_bench(dev, reps: int = 3):
                         "kernels_ms": {k: round(v[0] / v[1], 3) for k, v in kt.items()}}
         if ref is None:
             ref = (U.clone(), C.clone())
+        elif variant == "hybrid":
+            out["hybrid_U_C_identical_to_pairwise"] = bool(torch.equal(U, ref[0]) and torch.equal(C, ref[1]))
         else:
             out["triplet_U_equal"] = bool(torch.equal(U, ref[0]))
             rel = ((C.double() - ref[1].double()).abs() / ref[1].double().abs().clamp_min(1e-300))
             rel = torch.where(ref[1] == 0, (C != 0).double(), rel)
             out["triplet_vs_pairwise_max_rel"] = float(rel.max().item())
         del ws
+    return out
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def pipeline_bench(dev, n: int, Dg, C, workload: str, reps: int = 3):
+    """The steps around the two passes at the benchmark size, each against the HBM
+    roofline (8 TB/s) with its algorithmic bytes: the distance front end (writes
+    4 n^2 bytes, reads the points), local depths (reads 4 n^2), the strong-tie
+    count and scan (reads 4 n^2) and fill (reads each row up to its last edge,
+    writes 8 bytes per edge)."""
+    import torch
+
+    from paper_2307_16652_amd import pald, synth
+
+    def timed(fn):
+        fn(False)
+        torch.cuda.synchronize()
+        pald.timings_collect()
+        for _ in range(reps):
+            fn(True)
+        torch.cuda.synchronize()
+        return {k: v[0] / v[1] for k, v in pald.timings_collect().items()}
+
+    def hbm(nbytes, ms):
+        gbs = nbytes / (ms / 1e3) / 1e9
+        return {"ms": round(ms, 4), "bytes": int(nbytes), "GB_per_s": round(gbs, 1),
+                "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)}
+
+    out = {}
+    fronts = [("aniso16d_points_dim16_euclidean", synth.aniso16d_points(n=n, seed=5), "euclidean")]
+    if workload == "grid3d":
+        fronts.insert(0, ("grid3d_points_dim3_sqeuclidean", synth.grid3d_points(n=n, seed=SEED), "sqeuclidean"))
+    Dtmp = torch.empty((n, n), dtype=torch.float32, device=dev)
+    for name, P, metric in fronts:
+        Pg = torch.from_numpy(np.ascontiguousarray(P)).to(dev)
+        t = timed(lambda on: pald.distances(Pg, metric, timing=on, out=Dtmp))
+        rec = hbm(4.0 * n * n + 8.0 * P.size, t["distances"])
+        rec["ops_per_pair_and_dim"] = 2
+        if name.startswith("grid3d"):
+            rec["equals_benchmark_D"] = bool(torch.equal(Dtmp, Dg))
+        out[name] = rec
+    del Dtmp
+    depth = torch.empty(n, dtype=torch.float32, device=dev)
+    t = timed(lambda on: pald.local_depths(C, timing=on, out=depth))
+    rec = hbm(4.0 * n * n + 4.0 * n, t["local_depths"])
+    rec["sum_minus_half_n"] = float(depth.double().sum().item() - n / 2)
+    out["local_depths"] = rec
+    thr = float(torch.diagonal(C).double().mean().item() / 2)
+    t = timed(lambda on: pald.strong_ties(C, thr, timing=on))
+    row_ptr, col, val = pald.strong_ties(C, thr)
+    nnz = int(row_ptr[-1].item())
+    out["strong_ties"] = {"threshold": round(thr, 9), "threshold_rule": "half the mean of diag(C) (an example)",
+                          "edges": nnz,
+                          "count_scan": hbm(4.0 * n * n + 8.0 * (n + 1), t["strong_ties_count"]),
+                          "fill_ms": round(t["strong_ties_fill"], 4)}
     return out
 
 
@@ -223,6 +283,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-matrix batched measurement")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the distance front end, local depths and strong-tie measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise kernel that reads and writes 1 GiB, so a "
                          "counter profile can scale FETCH_SIZE / WRITE_SIZE")
@@ -335,6 +397,10 @@ def main():
         extra["variants_n4096"] = variants_bench(dev)
         progress(f"variants: {extra['variants_n4096']}")
     extra["pass1_focus_lane_ops_frac"] = round(p1_ops / (p1_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)
+    if not args.no_pipeline:
+        progress("pipeline: distances, local depths, strong ties")
+        extra["pipeline"] = pipeline_bench(dev, n, Dg, C, args.workload)
+        progress(f"pipeline: {extra['pipeline']}")
 
     base = None
     if not args.no_cpu_baseline:

@@ -66,8 +66,12 @@ enum {
     PALD_VARIANT_AUTO = 0,     /* library choice (currently pairwise) */
     PALD_VARIANT_PAIRWISE = 1, /* Section 3 pairwise algorithm: output-stationary
                                   (x,y) tiles for U, (x,z) tiles for C */
-    PALD_VARIANT_TRIPLET = 2   /* Section 3 triplet algorithm: one visit per
+    PALD_VARIANT_TRIPLET = 2,  /* Section 3 triplet algorithm: one visit per
                                   unordered triple, shared comparisons */
+    PALD_VARIANT_HYBRID = 3    /* triplet pass 1 + pairwise pass 2, the mix the
+                                  appendix's per-pass breakdown suggests; U and
+                                  C equal the pairwise variant's bit for bit;
+                                  y_chunks applies, z_chunks must be 0 */
 };
 
 /* Accumulation of the cohesion sums. */

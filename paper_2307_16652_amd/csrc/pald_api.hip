@@ -58,7 +58,7 @@ pald_status read_opts(const pald_options *o, Opts &out) {
     if (!o) return PALD_OK;
     for (int r : o->reserved)
         if (r != 0) return PALD_ERR_UNSUPPORTED;
-    if (o->variant < PALD_VARIANT_AUTO || o->variant > PALD_VARIANT_TRIPLET) return PALD_ERR_UNSUPPORTED;
+    if (o->variant < PALD_VARIANT_AUTO || o->variant > PALD_VARIANT_HYBRID) return PALD_ERR_UNSUPPORTED;
     if (o->accum != PALD_ACC_COMPENSATED && o->accum != PALD_ACC_F64) return PALD_ERR_UNSUPPORTED;
     if (o->y_chunks < 0 || o->z_chunks < 0) return PALD_ERR_ARG;
     if (o->flags & ~PALD_FLAG_TIMING) return PALD_ERR_UNSUPPORTED;
@@ -114,7 +114,8 @@ pald_status make_plan(int64_t n, const Opts &o, Plan &p) {
     size_t off = 0;
     p.off_w = off;
     off = align_up(off + (size_t)n * (size_t)p.ldw * sizeof(float), ALIGN);
-    p.need_u_scratch = p.z_chunks > 1;
+    // a split pass 1 accumulates into U; the hybrid's triplet pass 1 always does
+    p.need_u_scratch = p.z_chunks > 1 || o.variant == PALD_VARIANT_HYBRID;
     p.off_u = off;
     if (p.need_u_scratch) off = align_up(off + (size_t)n * (size_t)n * sizeof(int32_t), ALIGN);
     p.off_part = off;
@@ -286,7 +287,7 @@ pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd, int32_t *U,
     Opts o;
     if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
     if (!D || !U || n < 2 || ldd < n || ldu < n) return PALD_ERR_ARG;
-    if (o.variant == PALD_VARIANT_TRIPLET)
+    if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID)
         return triplet_focus(D, n, ldd, U, ldu, (hipStream_t)stream, (o.flags & PALD_FLAG_TIMING) != 0);
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
@@ -305,6 +306,7 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
         if (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
         return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, timing);
     }
+    if (o.variant == PALD_VARIANT_HYBRID && o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
     if (ws_bytes < p.bytes) return PALD_ERR_ARG;
@@ -316,7 +318,16 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
         Ub = reinterpret_cast<int32_t *>(base + p.off_u);
         ldub = n;
     }
-    if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, p.ldw, p, s, timing); st != PALD_OK) return st;
+    if (o.variant == PALD_VARIANT_HYBRID) {
+        // triplet pass 1 (one visit per unordered triple, integer atomics), then W
+        if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
+        ScopedTiming tm(timing, 1, s);
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, p.ldw, n);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    } else if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, p.ldw, p, s, timing); st != PALD_OK) {
+        return st;
+    }
     double *part = p.y_chunks > 1 ? reinterpret_cast<double *>(base + p.off_part) : nullptr;
     return run_pass2(D, n, ldd, W, p.ldw, C, ldc, part, p, o.accum == PALD_ACC_F64, s, timing);
 }

@@ -10,6 +10,7 @@ fallback path.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Sequence
 
@@ -17,7 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpald.so")
 
 OK, ERR_ARG, ERR_INPUT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = range(6)
-VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2}
+VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2, "hybrid": 3}
 ACCUMS = {"compensated": 0, "f64": 1}
 FLAG_TIMING = 1
 TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
@@ -91,6 +92,29 @@ def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int =
 
 #: batched-mode settings written by paper_2307_16652_amd.tune for this GPU
 TUNING_PATH = os.path.join(PKG, "tuning", "batch_gfx950.json")
+
+
+VARIANT_TUNING_PATH = os.path.join(PKG, "tuning", "variants_gfx950.json")
+_variant_table = None
+
+
+def choose_variant(n: int) -> str:
+    """The variant measured fastest (tuning/variants_gfx950.json) at the largest
+    tuned size <= n (the smallest tuned size below that); "pairwise" if untuned."""
+    global _variant_table
+    if _variant_table is None:
+        try:
+            with open(VARIANT_TUNING_PATH) as f:
+                _variant_table = sorted((int(r["n"]), str(r["best"])) for r in json.load(f)["sizes"])
+        except (OSError, ValueError, KeyError):
+            _variant_table = []
+    if not _variant_table:
+        return "pairwise"
+    best = _variant_table[0][1]
+    for size, v in _variant_table:
+        if size <= n:
+            best = v
+    return best if best in VARIANTS else "pairwise"
 
 
 def load_tuning(path: str | None = None, timestamps: bool = False) -> BatchConfig | None:
@@ -253,6 +277,8 @@ def cohesion(D, *, variant: str = "auto", accum: str = "compensated", y_chunks: 
     """(U, C): focus sizes (int32, or None if want_u is False) and cohesion (float32)."""
     torch = _torch()
     n, ldd = _check_matrix(D)
+    if variant == "auto" and accum == "compensated" and z_chunks == 0:
+        variant = choose_variant(n)
     opts = dict(variant=variant, accum=accum, y_chunks=y_chunks, z_chunks=z_chunks, timing=timing)
     o = make_options(**opts)
     if ws is None:

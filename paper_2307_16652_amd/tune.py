@@ -1,6 +1,7 @@
 """Autotuner of the batched mode.
 
     python -m paper_2307_16652_amd.tune [--out PATH] [--reps 3]
+    python -m paper_2307_16652_amd.tune --variants [--out PATH]
 
 Searches, on the 2000-matrix batch (n uniform in [32, 1024], 2-5 Gaussian
 clusters in R^4), for
@@ -15,6 +16,11 @@ by coordinate descent on the measured time of one whole batched launch
 tuning/batch_gfx950.json, which `pald.load_tuning()` (and so `bench.py`)
 picks up.  The tile shapes of the batched kernel are fixed at build time by
 its register budget; they are not part of this search.
+
+With --variants it instead times the pairwise, hybrid (triplet pass 1 +
+pairwise pass 2) and triplet variants of the single-matrix path on Gaussian
+mixtures of several sizes and writes, per size, the fastest one to
+tuning/variants_gfx950.json, which `pald.cohesion(variant="auto")` follows.
 """
 from __future__ import annotations
 
@@ -136,11 +142,57 @@ def tune(reps: int = 3, out: str | None = None) -> dict:
     return result
 
 
+VARIANT_SIZES = (256, 512, 1024, 2048, 4096, 8192)
+
+
+def tune_variants(reps: int = 3, out: str | None = None) -> dict:
+    import torch
+
+    from . import pald, synth
+
+    pald.load_library()
+    dev = torch.device("cuda:0")
+    rows = []
+    for n in VARIANT_SIZES:
+        Dg = torch.from_numpy(synth.mixture8d(n=n, seed=2)).to(dev)
+        ms = {}
+        for variant in ("pairwise", "hybrid", "triplet"):
+            ws = pald.workspace(n, dev, variant=variant)
+            U, C = pald.cohesion(Dg, variant=variant, ws=ws)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pald.cohesion(Dg, variant=variant, ws=ws, out_u=U, out_c=C)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms[variant] = round(float(np.median(times)), 3)
+            del ws, U, C
+        best = min(ms, key=ms.get)
+        log(f"n={n}: {ms} -> {best}")
+        rows.append({"n": n, "ms": ms, "best": best})
+    result = {"arch": "gfx950", "workload": "mixture8d (6 Gaussian clusters in R^8), seed 2",
+              "sizes": rows}
+    path = out or pald.VARIANT_TUNING_PATH
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(result, f, indent=1)
+    log(f"-> {path}")
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser(description="autotune the batched PaLD mode")
     ap.add_argument("--out", default=None)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--variants", action="store_true", help="choose the single-matrix variant per size instead")
     args = ap.parse_args()
+    if args.variants:
+        print(json.dumps(tune_variants(args.reps, args.out)))
+        return
     r = tune(args.reps, args.out)
     print(json.dumps({k: v for k, v in r.items() if k != "trials"}))
 

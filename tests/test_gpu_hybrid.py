@@ -1,0 +1,69 @@
+"""The hybrid variant (triplet pass 1 + pairwise pass 2): parity with the oracle,
+and U and C bit-identical to the pairwise variant (same integers, same pass 2)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import assert_c_close, assert_u_equal, gpu_cohesion, log, to_gpu
+from paper_2307_16652_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_16652_amd import pald
+
+    pald.load_library()
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 65, 129, 257, 300])
+def test_hybrid_parity_and_identity(n):
+    D = synth.grid3d(n=n, seed=n) if n % 2 else synth.mixture8d(n=n, seed=n)
+    log(f"[hybrid] n={n}")
+    U, C = gpu_cohesion(D, variant="hybrid")
+    Uo, Co = oracle.pald(D)
+    assert_u_equal(U, Uo, f"hybrid n={n}")
+    assert_c_close(C, Co, what=f"hybrid n={n}")
+    Up, Cp = gpu_cohesion(D, variant="pairwise")
+    assert np.array_equal(U, Up)
+    assert np.array_equal(C.view(np.int32), Cp.view(np.int32))
+
+
+@pytest.mark.parametrize("y_chunks", [1, 3])
+def test_hybrid_splits_and_no_u(y_chunks):
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    D = synth.random_tie_matrix(200, (0.0, 1.0, 2.0), seed=4)
+    Uo, Co = oracle.pald(D)
+    U, C = pald.cohesion(to_gpu(D), variant="hybrid", y_chunks=y_chunks, want_u=False)
+    torch.cuda.synchronize()
+    assert U is None
+    assert_c_close(C.cpu().numpy(), Co, what=f"hybrid y_chunks={y_chunks}")
+    U1 = pald.focus_sizes(to_gpu(D), variant="hybrid")
+    torch.cuda.synchronize()
+    assert_u_equal(U1.cpu().numpy(), Uo, "hybrid focus sizes")
+
+
+def test_hybrid_rejects_z_split():
+    from paper_2307_16652_amd import pald
+
+    with pytest.raises(pald.PaldError) as e:
+        pald.cohesion(to_gpu(synth.uniform2d(n=64)), variant="hybrid", z_chunks=2)
+    assert e.value.status == pald.ERR_UNSUPPORTED
+
+
+def test_hybrid_mixture8d_n4096_sampled():
+    D = synth.mixture8d()
+    rows = np.sort(np.random.default_rng(6).choice(4096, size=24, replace=False))
+    U, C = gpu_cohesion(D, variant="hybrid")
+    Uo, Co = oracle.pald_rows(D, rows)
+    assert_u_equal(U[rows], Uo, "hybrid n=4096")
+    err = assert_c_close(C[rows], Co, what="hybrid n=4096")
+    log(f"  max rel err {err:.3e}")

@@ -21,7 +21,10 @@ The steps around the two passes:
   in CSR form (Section 2 and Section 6 read community structure off the
   cohesion matrix by thresholding it);
 * `distances` (`distance_oracle.c`) -- Euclidean or squared Euclidean
-  distances between points, the input Section 6 feeds to PaLD.
+  distances between points, the input Section 6 feeds to PaLD;
+* `graph_distances` (`distance_oracle.c`) -- all-pairs shortest-path hop
+  counts of an unweighted graph, the input of the appendix's collaboration-
+  network runs (unreachable pairs at distance n).
 """
 from __future__ import annotations
 
@@ -66,6 +69,8 @@ def _load():
         lib.pald_oracle_full.restype = ctypes.c_int
         lib.pald_oracle_distances.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64]
         lib.pald_oracle_distances.restype = ctypes.c_int
+        lib.pald_oracle_graph_distances.argtypes = [vp, vp, i64, vp, i64, vp, i64]
+        lib.pald_oracle_graph_distances.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -172,4 +177,25 @@ def distances(P, metric: str = "euclidean", rows=None) -> np.ndarray:
                                        out.ctypes.data, n)
     if rc != 0:
         raise RuntimeError("pald_oracle_distances failed (bad arguments)")
+    return out
+
+
+def graph_distances(row_ptr, col, n: int, rows=None) -> np.ndarray:
+    """Hop-distance matrix (or rows `rows`) of the unweighted graph in CSR form,
+    float32, unreachable pairs = n, by one breadth-first search per row."""
+    row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int64))
+    col = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    if row_ptr.shape != (n + 1,) or row_ptr[0] != 0 or row_ptr[-1] > col.size or (np.diff(row_ptr) < 0).any():
+        raise ValueError("row_ptr must be a CSR offset array of length n + 1")
+    if rows is None:
+        out = np.empty((n, n), dtype=np.float32)
+        rp, nr = None, n
+    else:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
+        out = np.empty((rows.size, n), dtype=np.float32)
+        rp, nr = rows.ctypes.data, rows.size
+    rc = _load().pald_oracle_graph_distances(row_ptr.ctypes.data, col.ctypes.data if col.size else None, n,
+                                             rp, nr, out.ctypes.data, n)
+    if rc != 0:
+        raise RuntimeError("pald_oracle_graph_distances failed (bad arguments)")
     return out

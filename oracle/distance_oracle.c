@@ -18,9 +18,13 @@
  * diagonal are properties the tests check.  Compiled without contraction of
  * other multiply-adds and without fast-math.  Shares no code with the GPU
  * library.
+ *
+ * The second function below gives the graph version of the front end
+ * (shortest-path hop counts), one plain breadth-first search per row.
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 enum { ORACLE_METRIC_EUCLIDEAN = 0, ORACLE_METRIC_SQEUCLIDEAN = 1 };
 enum { ORACLE_F32 = 0, ORACLE_F64 = 1 };
@@ -63,4 +67,59 @@ int pald_oracle_distances(const void *P, int dtype, int64_t n, int64_t dim,
         }
     }
     return 0;
+}
+
+/*
+ * Graph front end: all-pairs shortest-path (hop) distances of an unweighted
+ * graph (the paper builds the distance matrices of its collaboration-network
+ * experiments this way, appendix on SNAP datasets).  The graph is CSR on the
+ * host: the neighbours of v are col[row_ptr[v] .. row_ptr[v+1]); neighbours
+ * outside [0, n) are ignored.  One breadth-first search per source row:
+ * D[s][v] = number of edges on a shortest path from s to v, D[s][s] = 0, and
+ * n for a vertex that s cannot reach (larger than every hop distance, so it
+ * compares like +infinity).  rows == NULL: all n rows in order.
+ * Returns 0, or -1 on bad arguments or allocation failure.
+ */
+int pald_oracle_graph_distances(const int64_t *row_ptr, const int32_t *col, int64_t n,
+                                const int64_t *rows, int64_t nrows, float *D_rows, int64_t ldd)
+{
+    if (!row_ptr || n < 1 || ldd < n)
+        return -1;
+    if (!rows)
+        nrows = n;
+    int64_t *dist = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *queue = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    if (!dist || !queue) {
+        free(dist);
+        free(queue);
+        return -1;
+    }
+    int rc = 0;
+    for (int64_t r = 0; r < nrows && rc == 0; ++r) {
+        const int64_t s = rows ? rows[r] : r;
+        if (s < 0 || s >= n) {
+            rc = -1;
+            break;
+        }
+        for (int64_t v = 0; v < n; ++v)
+            dist[v] = -1;
+        int64_t head = 0, tail = 0;
+        dist[s] = 0;
+        queue[tail++] = s;
+        while (head < tail) {
+            const int64_t u = queue[head++];
+            for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                const int64_t w = col[e];
+                if (w < 0 || w >= n || dist[w] >= 0)
+                    continue;
+                dist[w] = dist[u] + 1;
+                queue[tail++] = w;
+            }
+        }
+        for (int64_t v = 0; v < n; ++v)
+            D_rows[r * ldd + v] = (float)(dist[v] >= 0 ? dist[v] : n);
+    }
+    free(dist);
+    free(queue);
+    return rc;
 }

@@ -186,6 +186,35 @@ def batch_points(i: int, n: int, seed: int = 4) -> np.ndarray:
     return P[rng.permutation(n)]
 
 
+def collab_graph(n: int = 16384, papers: int | None = None, seed: int = 6):
+    """A seeded stand-in for a collaboration network: `papers` (default 2n)
+    papers each join 2-6 authors drawn with heavy-tailed activity weights
+    (Pareto, shape 1.5), and every paper links its authors pairwise.  Returns
+    the undirected simple graph as CSR (row_ptr int64 [n+1], col int32, both
+    directions stored, neighbours sorted, no self-loops).  Authors on no paper
+    are isolated vertices."""
+    rng = np.random.default_rng(seed)
+    papers = 2 * n if papers is None else int(papers)
+    act = rng.pareto(1.5, size=n) + 1.0
+    A = rng.choice(n, size=(papers, 6), p=act / act.sum())
+    K = rng.integers(2, 7, size=papers)
+    us, vs = [], []
+    for j in range(6):
+        for l in range(j + 1, 6):
+            m = l < K
+            us.append(A[m, j])
+            vs.append(A[m, l])
+    u = np.concatenate(us).astype(np.int64)
+    v = np.concatenate(vs).astype(np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    key = np.unique(np.concatenate([u * n + v, v * n + u]))
+    src, dst = key // n, key % n
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, src + 1, 1)
+    return np.cumsum(row_ptr), dst.astype(np.int32)
+
+
 # ----------------------------------------------------------------------------
 # distance matrices of the named workloads
 

@@ -9,7 +9,10 @@ strong-tie export and the distance front end (CPU only).
   comprehension on random matrices, the extreme thresholds, entries equal to
   the threshold, the diagonal, the two-cluster example;
 * distances: integer coordinates against exact integer arithmetic, scaled
-  Pythagorean triples, scipy's cdist, symmetry and zero diagonal.
+  Pythagorean triples, scipy's cdist, symmetry and zero diagonal;
+* graph distances: paths, cycles, complete and grid graphs in closed form,
+  components and isolated vertices (distance n), scipy's breadth-first
+  shortest paths on collaboration-graph stand-ins.
 """
 from __future__ import annotations
 
@@ -205,3 +208,74 @@ def test_distances_bad_arguments():
         oracle.distances(np.zeros((3, 2)), "manhattan")
     with pytest.raises(RuntimeError):
         oracle.distances(np.zeros((3, 2)), rows=[3])
+
+
+# ---------------------------------------------------------------------------
+# graph distances (all-pairs shortest-path hop counts)
+
+
+def csr_of(n, edges):
+    adj = [set() for _ in range(n)]
+    for u, v in edges:
+        if u != v:
+            adj[u].add(v)
+            adj[v].add(u)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum([len(a) for a in adj])
+    col = np.array([w for a in adj for w in sorted(a)], dtype=np.int32)
+    return row_ptr, col
+
+
+def test_graph_distances_closed_forms():
+    n = 9
+    idx = np.arange(n)
+    rp, col = csr_of(n, [(i, i + 1) for i in range(n - 1)])  # path
+    assert np.array_equal(oracle.graph_distances(rp, col, n), np.abs(idx[:, None] - idx[None, :]).astype(np.float32))
+    rp, col = csr_of(n, [(i, (i + 1) % n) for i in range(n)])  # cycle
+    d = np.abs(idx[:, None] - idx[None, :])
+    assert np.array_equal(oracle.graph_distances(rp, col, n), np.minimum(d, n - d).astype(np.float32))
+    rp, col = csr_of(n, [(i, j) for i in range(n) for j in range(i)])  # complete
+    assert np.array_equal(oracle.graph_distances(rp, col, n), (1 - np.eye(n)).astype(np.float32))
+    r, c = 4, 5  # grid: Manhattan distance
+    node = lambda i, j: i * c + j  # noqa: E731
+    edges = [(node(i, j), node(i, j + 1)) for i in range(r) for j in range(c - 1)]
+    edges += [(node(i, j), node(i + 1, j)) for i in range(r - 1) for j in range(c)]
+    rp, col = csr_of(r * c, edges)
+    ij = np.array([(i, j) for i in range(r) for j in range(c)])
+    man = np.abs(ij[:, None, :] - ij[None, :, :]).sum(-1)
+    assert np.array_equal(oracle.graph_distances(rp, col, r * c), man.astype(np.float32))
+
+
+def test_graph_distances_components_and_isolated_vertices():
+    n = 7
+    rp, col = csr_of(n, [(0, 1), (1, 2), (3, 4)])  # {0,1,2}, {3,4}, {5}, {6}
+    D = oracle.graph_distances(rp, col, n)
+    comp = np.array([0, 0, 0, 1, 1, 2, 3])
+    assert (D[comp[:, None] != comp[None, :]] == n).all()
+    assert D[0, 2] == 2 and D[3, 4] == 1 and (np.diag(D) == 0).all()
+    rp, col = csr_of(3, [])
+    assert np.array_equal(oracle.graph_distances(rp, col, 3), np.array([[0, 3, 3], [3, 0, 3], [3, 3, 0]], np.float32))
+
+
+def test_graph_distances_match_scipy_on_collaboration_graphs():
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+
+    from paper_2307_16652_amd import synth
+
+    for n, seed in ((60, 1), (300, 2), (1000, 3)):
+        rp, col = synth.collab_graph(n=n, papers=n // 2, seed=seed)
+        A = csr_matrix((np.ones(col.size), col, rp), shape=(n, n))
+        ref = shortest_path(A, directed=False, unweighted=True)
+        ref[np.isinf(ref)] = n
+        D = oracle.graph_distances(rp, col, n)
+        assert np.array_equal(D, ref.astype(np.float32)), (n, seed)
+        rows = [0, n - 1, n // 2]
+        assert np.array_equal(oracle.graph_distances(rp, col, n, rows=rows), D[rows])
+
+
+def test_graph_distances_ignore_out_of_range_neighbours():
+    rp = np.array([0, 2, 3, 4], dtype=np.int64)
+    col = np.array([1, 7, 0, -1], dtype=np.int32)  # 7 and -1 are not vertices
+    assert np.array_equal(oracle.graph_distances(rp, col, 3),
+                          np.array([[0, 1, 3], [1, 0, 3], [3, 3, 0]], np.float32))

@@ -81,6 +81,10 @@ DIST_MUTANTS = {
     "same_point_twice": ("- coord(P, dtype, ldp, y, k)", "- coord(P, dtype, ldp, x, k)"),
     "f64_read_as_f32": ("if (dtype == ORACLE_F64)", "if (0)"),
     "abs_not_square": ("acc = fma(delta, delta, acc);", "acc = acc + fabs(delta);"),
+    "hops_not_counted": ("dist[w] = dist[u] + 1;", "dist[w] = dist[u];"),
+    "source_at_one": ("dist[s] = 0;", "dist[s] = 1;"),
+    "unreachable_at_n_minus_1": ("(float)(dist[v] >= 0 ? dist[v] : n)", "(float)(dist[v] >= 0 ? dist[v] : n - 1)"),
+    "depth_first": ("const int64_t u = queue[head++];", "const int64_t u = queue[--tail];"),
 }
 
 
@@ -101,10 +105,15 @@ def test_distance_mutant_is_caught(name, tmp_path, monkeypatch):
     i64, vp = ctypes.c_int64, ctypes.c_void_p
     lib.pald_oracle_distances.argtypes = [vp, ctypes.c_int, i64, i64, i64, ctypes.c_int, vp, i64, vp, i64]
     lib.pald_oracle_distances.restype = ctypes.c_int
+    lib.pald_oracle_graph_distances.argtypes = [vp, vp, i64, vp, i64, vp, i64]
+    lib.pald_oracle_graph_distances.restype = ctypes.c_int
     monkeypatch.setattr(oracle, "_lib", lib)
     caught = []
     for pin in (ta.test_distances_integer_coordinates_exact, ta.test_distances_pythagorean,
-                ta.test_distances_match_scipy_and_are_symmetric):
+                ta.test_distances_match_scipy_and_are_symmetric, ta.test_graph_distances_closed_forms,
+                ta.test_graph_distances_components_and_isolated_vertices,
+                ta.test_graph_distances_match_scipy_on_collaboration_graphs,
+                ta.test_graph_distances_ignore_out_of_range_neighbours):
         try:
             pin()
         except AssertionError:

@@ -171,6 +171,34 @@ pald_status pald_distances(const void *P, int32_t dtype, int64_t n, int64_t dim,
                            int32_t metric, float *D, int64_t ldd, void *stream, uint32_t flags);
 
 /*
+ * Graph front end: all-pairs shortest-path hop counts of an unweighted graph,
+ * the distance matrices of the paper's collaboration-network runs (appendix,
+ * SNAP datasets).  D[s][v] = number of edges on a shortest s-v path,
+ * D[s][s] = 0, and n for pairs in different components (n exceeds every hop
+ * count, so PaLD's comparisons treat it exactly like +infinity while D stays
+ * finite).  The graph must be undirected for D to be symmetric: store both
+ * directions of every edge.
+ *   row_ptr [n + 1]  int64 CSR offsets, device: the neighbours of v are
+ *                    col[row_ptr[v] .. row_ptr[v+1]); offsets are clamped to
+ *                    [0, nnz], so a malformed array cannot cause reads past col
+ *   col     [nnz]    int32 neighbour ids, device (NULL if nnz = 0); ids outside
+ *                    [0, n) are ignored
+ *   D       [n x ldd] float32 output, device; every entry of the n x n block written
+ *   ws      device workspace, 8-byte aligned: at least 24 n bytes (one search
+ *           batch of 64 sources at a time);
+ *           pald_graph_distances_workspace_bytes(n) runs up to 1024 batches
+ *           concurrently
+ *   flags   0 or PALD_FLAG_TIMING (kind 12)
+ * Errors: PALD_ERR_ARG for null row_ptr/D/ws, null col with nnz > 0, n < 1,
+ * nnz < 0, ldd < n, a small or misaligned ws; PALD_ERR_UNSUPPORTED for
+ * n > 2^31-1 or an unknown flag.
+ */
+size_t pald_graph_distances_workspace_bytes(int64_t n);
+pald_status pald_graph_distances(const int64_t *row_ptr, const int32_t *col, int64_t nnz, int64_t n,
+                                 float *D, int64_t ldd, void *ws, size_t ws_bytes, void *stream,
+                                 uint32_t flags);
+
+/*
  * Local depths (Section 2: cohesion partitions the local depth of Eq. (LD),
  * l_x = sum_z c_xz): depth[x] = (float)(sum_z C[x][z]), summed in float64 in
  * a fixed order.  With C from pald_cohesion the relative error of each depth
@@ -322,7 +350,8 @@ void pald_batch_graph_destroy(pald_batch_graph *graph);
  * 1 weight preparation, 2 pass-2 cohesion, 3 cross-chunk finalize,
  * 4 batched persistent kernel, 5 triplet pass 1, 6 triplet pass 2,
  * 7 triplet finalize, 8 distances, 9 local depths, 10 strong-tie count and
- * scan, 11 strong-tie fill.  Returns the number of kinds defined (12).
+ * scan, 11 strong-tie fill, 12 graph distances.  Returns the number of kinds
+ * defined (13).
  */
 int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds);
 

@@ -131,3 +131,94 @@ __global__ __launch_bounds__(DIST_THREADS) void distances_kernel(const T *__rest
 }
 
 }  // namespace pald
+
+// ---------------------------------------------------------------------------
+// Graph front end: all-pairs shortest-path hop counts of an unweighted graph
+// (the distance matrices of the appendix's collaboration-network runs).
+//
+// Multi-source breadth-first search, 64 sources per workgroup: every vertex
+// v keeps 64-bit words visit[v] (sources that have reached v) and front[v]
+// (sources that reached v in the last level).  A level sets, for every v,
+//   next[v] = (OR over neighbours u of front[u]) & ~visit[v]
+// -- the bottom-up step for all 64 searches at once -- and writes the level
+// to D[s][v] for every source s whose bit is new.  The searches end when a
+// level reaches nothing.  Vertices no source of the batch reaches get n
+// (larger than any hop count, so it compares like +infinity); D[s][s] = 0.
+// The level loop needs only workgroup barriers: each workgroup owns its 64
+// rows of D and its three words per vertex in the workspace.
+//
+// Work per level is one pass over the edges; the 64 output rows are written
+// once each, in coalesced stores (lanes hold consecutive v).
+constexpr int BFS_THREADS = 1024;
+constexpr int BFS_SOURCES = 64;
+
+__global__ __launch_bounds__(BFS_THREADS) void graph_bfs_kernel(const int64_t *__restrict__ row_ptr,
+                                                                const int32_t *__restrict__ col, int64_t nnz,
+                                                                int64_t n, float *__restrict__ D, int64_t ldd,
+                                                                uint64_t *__restrict__ ws, int64_t batch0) {
+    const int64_t s0 = (batch0 + (int64_t)blockIdx.x) * BFS_SOURCES;
+    const int nsrc = (int)min<int64_t>(BFS_SOURCES, n - s0);
+    const uint64_t all = nsrc == 64 ? ~0ull : ((1ull << nsrc) - 1ull);
+    uint64_t *visit = ws + (int64_t)blockIdx.x * 3 * n;
+    uint64_t *cur = visit + n;
+    uint64_t *nxt = cur + n;
+    const int t = threadIdx.x;
+
+    for (int64_t v = t; v < n; v += BFS_THREADS) {
+        const uint64_t m = (v >= s0 && v < s0 + nsrc) ? (1ull << (v - s0)) : 0ull;
+        visit[v] = m;
+        cur[v] = m;
+    }
+    __syncthreads();
+
+    for (int level = 1;; ++level) {
+        int any = 0;
+        for (int64_t v = t; v < n; v += BFS_THREADS) {
+            const uint64_t vis = visit[v];
+            uint64_t acc = 0;
+            if (vis != all) {
+                const int64_t e0 = min(max(row_ptr[v], (int64_t)0), nnz);
+                const int64_t e1 = min(max(row_ptr[v + 1], e0), nnz);
+                int64_t e = e0;
+                for (; e + 4 <= e1; e += 4) {  // four independent loads in flight
+                    uint32_t u[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) u[k] = (uint32_t)col[e + k];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (u[k] < (uint64_t)n) acc |= cur[u[k]];
+                }
+                for (; e < e1; ++e) {
+                    const uint32_t u = (uint32_t)col[e];
+                    if (u < (uint64_t)n) acc |= cur[u];
+                }
+                acc &= ~vis;
+            }
+            nxt[v] = acc;
+            if (acc) {
+                visit[v] = vis | acc;
+                any = 1;
+                const float lv = (float)level;
+                for (int b = 0; b < nsrc; ++b)
+                    if ((acc >> b) & 1ull) D[(s0 + b) * ldd + v] = lv;
+            }
+        }
+        __syncthreads();  // this level's words are visible to the whole workgroup
+        if (!__syncthreads_or(any)) break;
+        uint64_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+
+    // the diagonal, and every vertex a source never reached
+    const float far = (float)n;
+    for (int64_t v = t; v < n; v += BFS_THREADS) {
+        const uint64_t vis = visit[v];
+        for (int b = 0; b < nsrc; ++b) {
+            if (s0 + b == v)
+                D[(s0 + b) * ldd + v] = 0.0f;
+            else if (!((vis >> b) & 1ull))
+                D[(s0 + b) * ldd + v] = far;
+        }
+    }
+}

@@ -44,6 +44,10 @@ pald_status launch_distances(const T *P, int64_t n, int64_t dim, int64_t ldp, fl
 
 inline bool row_vec(const float *C, int64_t ldc) { return aligned16(C) && ldc % 4 == 0; }
 
+constexpr int64_t BFS_MAX_SLOTS = 1024;  // concurrent 64-source searches per launch
+
+inline size_t bfs_slot_bytes(int64_t n) { return (size_t)3 * (size_t)n * sizeof(uint64_t); }
+
 }  // namespace
 
 extern "C" {
@@ -90,6 +94,30 @@ pald_status pald_strong_ties(const float *C, int64_t n, int64_t ldc, float thres
     ScopedTiming tm(timing, 11, s);
     ties_fill_kernel<<<row_blocks(n), AN_THREADS, 0, s>>>(C, n, ldc, threshold, row_ptr, col, val, cap);
     return launch_status();
+}
+
+size_t pald_graph_distances_workspace_bytes(int64_t n) {
+    if (n < 1) return 0;
+    const int64_t slots = std::min<int64_t>(ceil_div(n, BFS_SOURCES), BFS_MAX_SLOTS);
+    return align_up((size_t)slots * bfs_slot_bytes(n), ALIGN);
+}
+
+pald_status pald_graph_distances(const int64_t *row_ptr, const int32_t *col, int64_t nnz, int64_t n, float *D,
+                                 int64_t ldd, void *ws, size_t ws_bytes, void *stream, uint32_t flags) {
+    if (!row_ptr || !D || !ws || n < 1 || ldd < n || nnz < 0 || (nnz > 0 && !col)) return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & 7u) != 0 || ws_bytes < bfs_slot_bytes(n)) return PALD_ERR_ARG;
+    if (n > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    if (flags & ~PALD_FLAG_TIMING) return PALD_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t batches = ceil_div(n, BFS_SOURCES);
+    const int64_t slots = std::min<int64_t>({batches, BFS_MAX_SLOTS, (int64_t)(ws_bytes / bfs_slot_bytes(n))});
+    for (int64_t b0 = 0; b0 < batches; b0 += slots) {
+        ScopedTiming tm((flags & PALD_FLAG_TIMING) != 0, 12, s);
+        const unsigned g = (unsigned)std::min<int64_t>(slots, batches - b0);
+        graph_bfs_kernel<<<g, BFS_THREADS, 0, s>>>(row_ptr, col, nnz, n, D, ldd, static_cast<uint64_t *>(ws), b0);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    return PALD_OK;
 }
 
 }  // extern "C"

@@ -32,8 +32,9 @@ inline pald_status launch_status() {
 // ---- timing records -------------------------------------------------------
 // Kinds: 0 pass-1 focus sizes, 1 weights, 2 pass-2 cohesion, 3 finalize,
 // 4 batched persistent kernel, 5-7 triplet pass 1 / pass 2 / finalize,
-// 8 distances, 9 local depths, 10 strong-tie count + scan, 11 strong-tie fill.
-constexpr int NUM_KINDS = 12;
+// 8 distances, 9 local depths, 10 strong-tie count + scan, 11 strong-tie fill,
+// 12 graph distances.
+constexpr int NUM_KINDS = 13;
 
 struct TimingRec {
     int kind;

@@ -23,7 +23,7 @@ ACCUMS = {"compensated": 0, "f64": 1}
 FLAG_TIMING = 1
 TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
                 "triplet_pass1", "triplet_pass2", "triplet_finalize", "distances", "local_depths",
-                "strong_ties_count", "strong_ties_fill")
+                "strong_ties_count", "strong_ties_fill", "graph_distances")
 DTYPES = {"float32": 0, "float64": 1}
 METRICS = {"euclidean": 0, "sqeuclidean": 1}
 INPUT_FLAGS = {1: "nan", 2: "inf", 4: "negative", 8: "asymmetric", 16: "nonzero_diagonal"}
@@ -36,6 +36,7 @@ EXPORTED = (
     "pald_batch_timestamps", "pald_batch_queue", "pald_batch_plan_destroy",
     "pald_batch_graph_create", "pald_batch_graph_launch", "pald_batch_graph_destroy",
     "pald_timings_collect", "pald_distances", "pald_local_depths", "pald_strong_ties",
+    "pald_graph_distances_workspace_bytes", "pald_graph_distances",
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
@@ -192,6 +193,10 @@ def load_library(path: str | None = None):
     lib.pald_local_depths.restype = i32
     lib.pald_strong_ties.argtypes = [vp, i64, i64, ctypes.c_float, vp, vp, vp, i64, vp, u32]
     lib.pald_strong_ties.restype = i32
+    lib.pald_graph_distances_workspace_bytes.argtypes = [i64]
+    lib.pald_graph_distances_workspace_bytes.restype = sz
+    lib.pald_graph_distances.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp, u32]
+    lib.pald_graph_distances.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -325,6 +330,29 @@ def distances(P, metric: str = "euclidean", *, timing: bool = False, out=None):
         max(P.stride(0), dim), METRICS[metric], D.data_ptr(), D.stride(0), _stream_ptr(P.device),
         FLAG_TIMING if timing else 0)
     _check(st, "pald_distances")
+    return D
+
+
+def graph_distances(row_ptr, col, n: int, *, timing: bool = False, out=None, ws=None):
+    """Hop-distance matrix D (float32, n x n; unreachable pairs = n) of the
+    undirected graph with CSR arrays row_ptr (int64 [n+1]) and col (int32),
+    torch tensors on the GPU."""
+    torch = _torch()
+    for a, dt, name in ((row_ptr, torch.int64, "row_ptr"), (col, torch.int32, "col")):
+        if not isinstance(a, torch.Tensor) or not a.is_cuda or a.dtype != dt or a.dim() != 1 or \
+                not a.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous 1-D {dt} tensor on a HIP (cuda) device")
+    if row_ptr.numel() != n + 1:
+        raise ValueError("row_ptr must have n + 1 entries")
+    lib = load_library()
+    D = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=row_ptr.device)
+    if ws is None:
+        ws = torch.empty(int(lib.pald_graph_distances_workspace_bytes(n)), dtype=torch.uint8,
+                         device=row_ptr.device)
+    st = lib.pald_graph_distances(row_ptr.data_ptr(), col.data_ptr() if col.numel() else None, col.numel(), n,
+                                  D.data_ptr(), D.stride(0), ws.data_ptr(), ws.numel(), _stream_ptr(row_ptr.device),
+                                  FLAG_TIMING if timing else 0)
+    _check(st, "pald_graph_distances")
     return D
 
 

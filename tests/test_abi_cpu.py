@@ -105,7 +105,7 @@ def test_timings_collect_without_records():
     k = len(pald.TIMING_KINDS)
     tot = (ctypes.c_double * k)()
     cnt = (ctypes.c_int64 * k)()
-    assert lib.pald_timings_collect(tot, cnt, k) == k == 12
+    assert lib.pald_timings_collect(tot, cnt, k) == k == 13
     assert list(cnt) == [0] * k
 
 
@@ -136,3 +136,22 @@ def test_front_end_and_analysis_argument_errors():
     assert lib.pald_strong_ties(f, 8, 7, 0.5, f, f, None, 4, None, 0) == pald.ERR_ARG
     assert lib.pald_strong_ties(f, 8, 8, float("nan"), f, f, None, 4, None, 0) == pald.ERR_ARG
     assert lib.pald_strong_ties(f, 8, 8, 0.5, f, f, None, 4, None, 8) == pald.ERR_UNSUPPORTED
+
+
+def test_graph_distances_argument_errors():
+    lib = pald.load_library()
+    f = ctypes.c_void_p(0x10000)
+    ws = 24 * 8
+    assert lib.pald_graph_distances_workspace_bytes(0) == 0
+    assert lib.pald_graph_distances_workspace_bytes(64) >= 24 * 64
+    # row_ptr, col, nnz, n, D, ldd, ws, ws_bytes, stream, flags
+    assert lib.pald_graph_distances(None, f, 4, 8, f, 8, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, None, 4, 8, f, 8, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, None, 8, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, f, 8, None, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, -1, 8, f, 8, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 0, f, 8, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, f, 7, f, ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, f, 8, f, ws - 8, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, f, 8, ctypes.c_void_p(0x10004), ws, None, 0) == pald.ERR_ARG
+    assert lib.pald_graph_distances(f, f, 4, 8, f, 8, f, ws, None, 2) == pald.ERR_UNSUPPORTED

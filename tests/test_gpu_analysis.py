@@ -223,3 +223,81 @@ def test_strong_ties_of_gpu_cohesion_agree_away_from_the_threshold():
     clear = np.abs(Co - t) > 2e-6 * t
     assert np.array_equal(A[clear], B[clear])
     log(f"[ties] n=900 edges {int(rp[-1])}, undecided {int((~clear).sum())}")
+
+
+# ---------------------------------------------------------------------------
+# graph distances
+
+
+def _graph_to_gpu(rp, col):
+    import torch
+
+    return torch.from_numpy(np.asarray(rp, np.int64)).cuda(), torch.from_numpy(np.asarray(col, np.int32)).cuda()
+
+
+@pytest.mark.parametrize("n,papers,seed", [(1, 0, 1), (2, 1, 1), (63, 20, 2), (64, 40, 3), (65, 30, 4),
+                                           (300, 150, 5), (1000, 2000, 6), (2500, 1200, 7)])
+def test_graph_distances_bit_exact(n, papers, seed):
+    import torch
+
+    rp, col = synth.collab_graph(n=n, papers=papers, seed=seed) if papers else \
+        (np.zeros(n + 1, np.int64), np.zeros(0, np.int32))
+    log(f"[graph] n={n} edges={int(rp[-1])}")
+    D = _pald().graph_distances(*_graph_to_gpu(rp, col), n)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), oracle.graph_distances(rp, col, n))
+
+
+def test_graph_distances_small_workspace_and_pitch():
+    """One 64-source batch at a time (minimal workspace), output with a row pitch."""
+    import torch
+
+    n = 700
+    rp, col = synth.collab_graph(n=n, papers=400, seed=8)
+    ref = oracle.graph_distances(rp, col, n)
+    ws = torch.empty(24 * n, dtype=torch.uint8, device="cuda")
+    big = torch.full((n, n + 5), -1.0, dtype=torch.float32, device="cuda")
+    D = _pald().graph_distances(*_graph_to_gpu(rp, col), n, ws=ws, out=big[:, :n])
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), ref)
+    assert (big[:, n:].cpu().numpy() == -1.0).all()
+
+
+def test_graph_distances_ignore_bad_neighbours_and_offsets():
+    """Out-of-range neighbour ids are skipped; offsets beyond nnz are clamped."""
+    import torch
+
+    rp = np.array([0, 2, 3, 4], np.int64)
+    col = np.array([1, 7, 0, -1], np.int32)
+    D = _pald().graph_distances(*_graph_to_gpu(rp, col), 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), oracle.graph_distances(rp, col, 3))
+    rp_bad = np.array([0, 2, 3, 99], np.int64)  # last row claims edges past nnz
+    D = _pald().graph_distances(*_graph_to_gpu(rp_bad, col), 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(D.cpu().numpy(), oracle.graph_distances(rp, col, 3))
+
+
+def test_graph_collaboration_n16384_sampled_then_pald():
+    """The collaboration-network stand-in at n = 16384: sampled rows bit-exact, D a valid
+    PaLD input (symmetric, zero diagonal), and PaLD on it against oracle rows."""
+    import torch
+
+    n = 16384
+    rp, col = synth.collab_graph(n=n)
+    D = _pald().graph_distances(*_graph_to_gpu(rp, col), n)
+    torch.cuda.synchronize()
+    rows = np.concatenate([[0, n - 1], np.sort(np.random.default_rng(10).choice(n, 14, replace=False))])
+    assert np.array_equal(D[torch.from_numpy(rows).cuda()].cpu().numpy(), oracle.graph_distances(rp, col, n, rows=rows))
+    assert torch.equal(D, D.T) and bool((torch.diagonal(D) == 0).all())
+    assert _pald().check_input(D) == []
+    U, C = _pald().cohesion(D)
+    torch.cuda.synchronize()
+    prow = rows[:6]
+    Dh = D.cpu().numpy()
+    Uo, Co = oracle.pald_rows(Dh, prow)
+    from gpu_helpers import assert_c_close, assert_u_equal
+
+    assert_u_equal(U[torch.from_numpy(prow).cuda()].cpu().numpy(), Uo, "collab n=16384")
+    err = assert_c_close(C[torch.from_numpy(prow).cuda()].cpu().numpy(), Co, what="collab n=16384")
+    log(f"[graph] n=16384 edges={int(rp[-1])} PaLD max rel err {err:.3e}")

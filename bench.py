@@ -221,9 +221,11 @@ HBM_PEAK_GBS = 8000.0
 def pipeline_bench(dev, n: int, Dg, C, workload: str, reps: int = 3):
     """The steps around the two passes at the benchmark size, each against the HBM
     roofline (8 TB/s) with its algorithmic bytes: the distance front end (writes
-    4 n^2 bytes, reads the points), local depths (reads 4 n^2), the strong-tie
-    count and scan (reads 4 n^2) and fill (reads each row up to its last edge,
-    writes 8 bytes per edge)."""
+    4 n^2 bytes, reads the points), the graph front end on the collaboration-
+    network stand-in (writes 4 n^2; also traversed edges/s, n x directed edges
+    per evaluation), local depths (reads 4 n^2), the strong-tie count and scan
+    (reads 4 n^2) and fill (reads each row up to its last edge, writes 8 bytes
+    per edge)."""
     import torch
 
     from paper_2307_16652_amd import pald, synth
@@ -255,7 +257,17 @@ def pipeline_bench(dev, n: int, Dg, C, workload: str, reps: int = 3):
         if name.startswith("grid3d"):
             rec["equals_benchmark_D"] = bool(torch.equal(Dtmp, Dg))
         out[name] = rec
-    del Dtmp
+    rp, colg = synth.collab_graph(n=n)
+    rpg = torch.from_numpy(rp).to(dev)
+    colgg = torch.from_numpy(colg).to(dev)
+    gws = torch.empty(int(pald.load_library().pald_graph_distances_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    t = timed(lambda on: pald.graph_distances(rpg, colgg, n, timing=on, out=Dtmp, ws=gws))
+    rec = hbm(4.0 * n * n, t["graph_distances"])
+    rec["edges_directed"] = int(rp[-1])
+    rec["G_traversed_edges_per_s"] = round(n * float(rp[-1]) / (t["graph_distances"] / 1e3) / 1e9, 1)
+    rec["max_finite_hops"] = int(Dtmp[Dtmp < n].max().item())
+    out["collab_graph_hop_distances"] = rec
+    del Dtmp, gws
     depth = torch.empty(n, dtype=torch.float32, device=dev)
     t = timed(lambda on: pald.local_depths(C, timing=on, out=depth))
     rec = hbm(4.0 * n * n + 4.0 * n, t["local_depths"])

@@ -93,16 +93,14 @@ __device__ __forceinline__ void focus_count8(int32_t (&c)[8], uint32_t x, const 
 
 // Cohesion terms of one x and four z for one second point y, both directions:
 //   in_j  = [t_j <= min(a, b_j)]
-//   rf_j (+)= in_j ? (t_j < b_j ? wx : whx) : 0          (c_xz, focus of x and y)
-//   rr_j (+)= in_j ? (t_j < a   ? wz_j : whz_j) : 0      (c_zx, focus of z and y)
+//   rf_j += in_j ? (t_j < b_j ? wx : whx) : 0          (c_xz, focus of x and y)
+//   rr_j += in_j ? (t_j < a   ? wz_j : whz_j) : 0      (c_zx, focus of z and y)
 // with a = d_xy, b_j = d_z_j y, t_j = d_x z_j (all as keys), wx = W_xy,
-// wz_j = W_z_j y and wh = w / 2.  ASSIGN starts new runs (rf = term) instead of
-// adding.  One block, so that every compare mask is read at least two
+// wz_j = W_z_j y and wh = w / 2.  One block, so that every compare mask is read at least two
 // instructions after it is written (the wait states a vector read of a
 // vector-written scalar register needs) and the four pairs interleave; the
 // compiler's own schedule funnels the masks through one or two registers.
 // Registers only, no memory access; EXEC is back to its entry value at exit.
-template <bool ASSIGN>
 __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], const uint32_t (&t)[4], uint32_t a,
                                                 const uint32_t (&b)[4], float wx, float whx, const float (&wz)[4],
                                                 const float (&whz)[4]) {
@@ -144,20 +142,7 @@ __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], 
         [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3]), [wx] "v"(wx), [whx] "v"(whx), [wz0] "v"(wz[0]),       \
         [wz1] "v"(wz[1]), [wz2] "v"(wz[2]), [wz3] "v"(wz[3]), [whz0] "v"(whz[0]), [whz1] "v"(whz[1]),         \
         [whz2] "v"(whz[2]), [whz3] "v"(whz[3])
-    if (ASSIGN) {
-        asm(PALD_T4_HEAD
-            "v_cndmask_b32_e64 %[rf0], 0, %[f0], %[i0]\n\t"
-            "v_cndmask_b32_e64 %[rr0], 0, %[g0], %[i0]\n\t"
-            "v_cndmask_b32_e64 %[rf1], 0, %[f1], %[i1]\n\t"
-            "v_cndmask_b32_e64 %[rr1], 0, %[g1], %[i1]\n\t"
-            "v_cndmask_b32_e64 %[rf2], 0, %[f2], %[i2]\n\t"
-            "v_cndmask_b32_e64 %[rr2], 0, %[g2], %[i2]\n\t"
-            "v_cndmask_b32_e64 %[rf3], 0, %[f3], %[i3]\n\t"
-            "v_cndmask_b32_e64 %[rr3], 0, %[g3], %[i3]"
-            : [rf0] "=&v"(rf[0]), [rf1] "=&v"(rf[1]), [rf2] "=&v"(rf[2]), [rf3] "=&v"(rf[3]),
-              [rr0] "=&v"(rr[0]), [rr1] "=&v"(rr[1]), [rr2] "=&v"(rr[2]), [rr3] "=&v"(rr[3]), PALD_T4_OPERANDS
-            : PALD_T4_INPUTS);
-    } else {
+    {
         // Adds only in the lanes whose pair is in the focus: EXEC is narrowed to
         // each pair's membership mask in turn and restored at the end, which
         // spares the select-with-zero of every term.
@@ -424,6 +409,10 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 #ifndef PALD_P2_RUN
 #define PALD_P2_RUN 12
 #endif
+// minimum waves per SIMD the pass-2 kernel is compiled for (its VGPR budget)
+#ifndef PALD_P2_MIN_WAVES
+#define PALD_P2_MIN_WAVES 3
+#endif
 template <int T, int RX, int KY>
 struct Pass2Cfg {
     static constexpr int RZ = 4;                        // z per thread (the term block's width)
@@ -478,15 +467,19 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
         }
     }
 
-    // forward (c_xz) and reverse (c_zx) accumulators
-    float sf[RX][RZ], cf[RX][RZ], rf[RX][RZ], sr[RX][RZ], cr[RX][RZ], rr[RX][RZ];
+    // forward (c_xz) and reverse (c_zx) accumulators: Kahan sums s and run
+    // accumulators r.  A run starts from the negated compensation left by the
+    // previous fold, so r holds (run sum - c) when the run ends -- the
+    // compensated summand of Kahan's algorithm -- and no separate compensation
+    // register stays live during a run.
+    float sf[RX][RZ], rf[RX][RZ], sr[RX][RZ], rr[RX][RZ];
     double af[RX][RZ], ar[RX][RZ];
 #pragma unroll
     for (int i = 0; i < RX; ++i)
 #pragma unroll
         for (int j = 0; j < RZ; ++j) {
-            sf[i][j] = cf[i][j] = rf[i][j] = 0.0f;
-            sr[i][j] = cr[i][j] = rr[i][j] = 0.0f;
+            sf[i][j] = rf[i][j] = 0.0f;
+            sr[i][j] = rr[i][j] = 0.0f;
             af[i][j] = ar[i][j] = 0.0;
         }
 
@@ -582,28 +575,21 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
                     uint32_t av[RX], bv[RZ];
                     float wx[RX], whx[RX], wz[RZ], whz[RZ];
                     load_row(y0 + yy, av, wx, whx, bv, wz, whz);
-                    if (yy == 0) {
 #pragma unroll
-                        for (int i = 0; i < RX; ++i)
-                            cohesion_terms4<true>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < RX; ++i)
-                            cohesion_terms4<false>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
-                    }
+                    for (int i = 0; i < RX; ++i)
+                        cohesion_terms4(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
                 }
-                // Kahan fold of the finished runs: sum - comp tracks the exact total.
+                // Kahan fold of the finished runs (r = run - c): s + r, with the
+                // new negated compensation -c = r - ((s + r) - s) left in r.
 #pragma unroll
                 for (int i = 0; i < RX; ++i)
 #pragma unroll
                     for (int j = 0; j < RZ; ++j) {
-                        float yk = rf[i][j] - cf[i][j];
-                        float tk = sf[i][j] + yk;
-                        cf[i][j] = (tk - sf[i][j]) - yk;
+                        float tk = sf[i][j] + rf[i][j];
+                        rf[i][j] = rf[i][j] - (tk - sf[i][j]);
                         sf[i][j] = tk;
-                        yk = rr[i][j] - cr[i][j];
-                        tk = sr[i][j] + yk;
-                        cr[i][j] = (tk - sr[i][j]) - yk;
+                        tk = sr[i][j] + rr[i][j];
+                        rr[i][j] = rr[i][j] - (tk - sr[i][j]);
                         sr[i][j] = tk;
                     }
             }
@@ -620,8 +606,8 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
 #pragma unroll
         for (int j = 0; j < RZ; ++j) {
             const int64_t z = Z0 + tz * RZ + j;
-            const double tf = F64 ? af[i][j] : ((double)sf[i][j] - (double)cf[i][j]);
-            const double tr = F64 ? ar[i][j] : ((double)sr[i][j] - (double)cr[i][j]);
+            const double tf = F64 ? af[i][j] : ((double)sf[i][j] + (double)rf[i][j]);
+            const double tr = F64 ? ar[i][j] : ((double)sr[i][j] + (double)rr[i][j]);
             if (out.tile) {
                 const int li = tx * RX + i, lj = tz * RZ + j;
                 out.tile[li * T + lj] = tf;
@@ -641,7 +627,7 @@ __device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ 
 }
 
 template <int T, int RX, int KY, bool F64>
-__global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT)) void pass2_cohesion_kernel(
+__global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT), PALD_P2_MIN_WAVES) void pass2_cohesion_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
     float *__restrict__ C, int64_t ldc, double *__restrict__ partial, int32_t y_per_chunk,
     int32_t vec_ok_d, int32_t vec_ok_w, int32_t tile0) {

@@ -42,6 +42,16 @@ struct BatchMatrix {
     int32_t vec_d;     // rows of D start on 16-byte boundaries (given an aligned base)
 };
 
+// A value every lane of the wave holds, moved to a scalar register (the item
+// and matrix records are read from LDS, which the compiler cannot prove
+// uniform; as scalars they take no vector registers across the tile body).
+__device__ __forceinline__ int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Item kinds.
 constexpr int32_t ITEM_PASS1 = 0;
 constexpr int32_t ITEM_PASS2 = 1;
@@ -50,13 +60,15 @@ constexpr int32_t ITEM_PASS2 = 1;
 #define PALD_BATCH_THREADS 256
 #endif
 #ifndef PALD_BATCH_MIN_BLOCKS
-#define PALD_BATCH_MIN_BLOCKS 2
+#define PALD_BATCH_MIN_BLOCKS 3
 #endif
 constexpr int BATCH_THREADS = PALD_BATCH_THREADS;
 // One pass-1 shape (64 x 64 tiles, 2 x 8 counters per thread) and one pass-2
-// shape (64 x 64 tiles, 4 x 4 pairs): both inlined in one kernel, the larger
-// single-matrix pass-1 register tile would push the kernel to one wave per
-// SIMD.
+// shape (64 x 64 tiles, 4 x 4 pairs), both inlined in one kernel compiled for
+// 3 waves per SIMD (168 VGPRs).  The tile functions get the thread index
+// through opaque_tid(), so the per-thread addressing they derive from it is
+// recomputed per work item instead of being held across the item loop; the
+// larger single-matrix pass-1 register tile would not fit that budget.
 constexpr int BATCH_P1_T = 64, BATCH_P1_RX = BATCH_THREADS == 256 ? 2 : 1;
 #ifndef PALD_P2_KY
 #define PALD_P2_KY 12
@@ -111,80 +123,84 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
         if (s_item >= total) break;  // uniform: every thread reads the same value
 
         {
-            const int32_t mi = s_it.x;
+            const int32_t mi = uniform_i32(s_it.x), kind = uniform_i32(s_it.y), tile = uniform_i32(s_it.z),
+                          chunk = uniform_i32(s_it.w);
+            const int64_t moff = uniform_i64(s_m.off), mwoff = uniform_i64(s_m.woff), mpoff = uniform_i64(s_m.poff);
+            const int32_t mldw = uniform_i32(s_m.ldw), mtiles1 = uniform_i32(s_m.tiles1),
+                          mychunks = uniform_i32(s_m.y_chunks), mypc = uniform_i32(s_m.y_per_chunk),
+                          mctr2 = uniform_i32(s_m.ctr2);
             if (stamps && tid == 0)
                 atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
-            const int64_t n = s_m.n;
-            const bool vec_d = d_aligned && s_m.vec_d;
-            if (s_it.y == ITEM_PASS1) {
+            const int64_t n = uniform_i32(s_m.n);
+            const bool vec_d = d_aligned && uniform_i32(s_m.vec_d);
+            if (kind == ITEM_PASS1) {
                 int32_t bx, by;
-                tri_tile(s_it.z, bx, by);
-                int32_t *Um = U ? U + s_m.off : nullptr;
-                pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(sm, D + s_m.off, n, n, Um, n, Wr + s_m.woff, s_m.ldw, bx, by, 0, n,
+                tri_tile(tile, bx, by);
+                int32_t *Um = U ? U + moff : nullptr;
+                pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(opaque_tid(), sm, D + moff, n, n, Um, n, Wr + mwoff, mldw, bx, by, 0, n,
                                                  false, vec_d);
                 __threadfence();  // release this thread's U / W stores at device scope
                 __syncthreads();
-                if (tid == 0) atomicAdd(&done1[s_it.x], 1u);
+                if (tid == 0) atomicAdd(&done1[mi], 1u);
             } else {
                 if (tid == 0) {
                     while (__hip_atomic_load(&done1[mi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                           (uint32_t)s_m.tiles1)
+                           (uint32_t)mtiles1)
                         __builtin_amdgcn_s_sleep(2);
                     __atomic_thread_fence(__ATOMIC_ACQUIRE);
                 }
                 __syncthreads();
                 __threadfence();  // acquire for every wave before reading the weights
                 int32_t bx, bz;
-                tri_tile(s_it.z, bx, bz);
-                const int64_t ybeg = (int64_t)s_it.w * s_m.y_per_chunk;
-                const int64_t yend = min(n, ybeg + (int64_t)s_m.y_per_chunk);
+                tri_tile(tile, bx, bz);
+                const int64_t ybeg = (int64_t)chunk * mypc;
+                const int64_t yend = min(n, ybeg + (int64_t)mypc);
                 constexpr int64_t TT2 = 2 * BATCH_P2_T * BATCH_P2_T;
                 Pass2Out out{nullptr, 0, nullptr, nullptr};
-                if (s_m.y_chunks == 1) {
-                    out.C = C + s_m.off;
+                if (mychunks == 1) {
+                    out.C = C + moff;
                     out.ldc = n;
                 } else {
-                    out.tile = Pr + s_m.poff + ((int64_t)s_it.z * s_m.y_chunks + s_it.w) * TT2;
+                    out.tile = Pr + mpoff + ((int64_t)tile * mychunks + chunk) * TT2;
                 }
-                pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false>(sm, D + s_m.off, n, n, Wr + s_m.woff, s_m.ldw,
+                pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff, mldw,
                                                                        out, bx, bz, ybeg, yend, vec_d, true);
-                if (s_m.y_chunks > 1) {
+                if (mychunks > 1) {
                     __threadfence();
                     __syncthreads();
                     if (tid == 0) {
-                        const uint32_t prev = atomicAdd(&ctr[1 + count + s_m.ctr2 + s_it.z], 1u);
-                        s_last = (prev == (uint32_t)(s_m.y_chunks - 1)) ? 1 : 0;
+                        const uint32_t prev = atomicAdd(&ctr[1 + count + mctr2 + tile], 1u);
+                        s_last = (prev == (uint32_t)(mychunks - 1)) ? 1 : 0;
                         if (s_last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
                     }
                     __syncthreads();
                     if (s_last) {
                         __threadfence();
-                        const int64_t nn = s_m.n;
-                        const int32_t chunks = s_m.y_chunks;
+                        const int32_t chunks = mychunks;
                         int32_t tbx, tbz;
-                        tri_tile(s_it.z, tbx, tbz);
+                        tri_tile(tile, tbx, tbz);
                         const int64_t X0 = (int64_t)tbx * BATCH_P2_T, Z0 = (int64_t)tbz * BATCH_P2_T;
-                        const double nm1 = (double)(nn - 1);
-                        const double *tiles = Pr + s_m.poff + (int64_t)s_it.z * chunks * TT2;
-                        float *Cm = C + s_m.off;
+                        const double nm1 = (double)(n - 1);
+                        const double *tiles = Pr + mpoff + (int64_t)tile * chunks * TT2;
+                        float *Cm = C + moff;
                         for (int e = tid; e < BATCH_P2_T * BATCH_P2_T; e += BATCH_THREADS) {
                             const int i = e / BATCH_P2_T, j = e % BATCH_P2_T;
                             const int64_t x = X0 + i, z = Z0 + j;
-                            if (x >= nn || z >= nn) continue;
+                            if (x >= n || z >= n) continue;
                             double sf = 0.0, sr = 0.0;
                             for (int32_t k = 0; k < chunks; ++k) {
                                 sf += tiles[k * TT2 + e];
                                 sr += tiles[k * TT2 + BATCH_P2_T * BATCH_P2_T + e];
                             }
-                            Cm[x * nn + z] = (float)(sf / nm1);
-                            if (tbx != tbz) Cm[z * nn + x] = (float)(sr / nm1);
+                            Cm[x * n + z] = (float)(sf / nm1);
+                            if (tbx != tbz) Cm[z * n + x] = (float)(sr / nm1);
                         }
                     }
                 }
             }
             if (stamps && tid == 0) {
                 __threadfence();
-                atomicMax((unsigned long long *)&stamps[2 * s_it.x + 1], (unsigned long long)wall_clock64());
+                atomicMax((unsigned long long *)&stamps[2 * mi + 1], (unsigned long long)wall_clock64());
             }
         }
         __syncthreads();  // LDS (tile buffers, s_item, s_it, s_m, s_last) is reused by the next item

@@ -171,6 +171,17 @@ __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], 
 #undef PALD_T4_INPUTS
 }
 
+// threadIdx.x, passed through an empty volatile asm: values derived from it
+// are then recomputed where a tile function is called instead of being
+// hoisted out of an enclosing loop (the persistent batched kernel calls the
+// tile functions once per work item; hoisted, those values would stay live
+// across every tile and push the kernel past its register budget).
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Upper-triangular tile enumeration: k -> (bx, by) with bx <= by, by-major.
 __device__ __forceinline__ void tri_tile(int32_t k, int32_t &bx, int32_t &by) {
     int32_t r = (int32_t)((sqrtf(8.0f * (float)k + 1.0f) - 1.0f) * 0.5f);
@@ -231,6 +242,10 @@ __device__ __forceinline__ float weight_of(int32_t u) { return (float)(1.0 / (do
 // if W != nullptr, the weights W) directly; with several it atomically adds
 // its counts into U, which must be zero on entry.
 
+// minimum waves per SIMD the pass-1 kernel is compiled for (its VGPR budget)
+#ifndef PALD_P1_MIN_WAVES
+#define PALD_P1_MIN_WAVES 4
+#endif
 template <int T, int RX, int RY, int KZ>
 struct Pass1Cfg {
     static constexpr int TX = T / RX;  // threads along x
@@ -249,13 +264,12 @@ struct Pass1Cfg {
 // by every thread of a workgroup of Pass1Cfg::NT threads; `sm` points to
 // Pass1Cfg::LDS_VEC uint4 of LDS.  U may be null in direct mode.
 template <int T, int RX, int RY, int KZ>
-__device__ __forceinline__ void pass1_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
+__device__ __forceinline__ void pass1_tile(int tid, uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            int32_t *__restrict__ U, int64_t ldu, float *__restrict__ W, int64_t ldw,
                                            int32_t bx, int32_t by, int64_t zbeg, int64_t zend, bool atomic_mode,
                                            bool vec_ok) {
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
     const int64_t X0 = (int64_t)bx * T, Y0 = (int64_t)by * T;
-    const int tid = threadIdx.x;
     const int tx = tid % Cfg::TX, ty = tid / Cfg::TX;
 
     // stationary keys a_ij = d_xy
@@ -346,7 +360,7 @@ __device__ __forceinline__ void pass1_tile(uint4 *sm, const float *__restrict__ 
 }
 
 template <int T, int RX, int RY, int KZ>
-__global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_kernel(
+__global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT), PALD_P1_MIN_WAVES) void pass1_focus_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
     float *__restrict__ W, int64_t ldw, int32_t z_per_chunk, int32_t atomic_mode, int32_t vec_ok, int32_t tile0) {
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
@@ -355,7 +369,7 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT)) void pass1_focus_ker
     tri_tile(tile0 + (int32_t)blockIdx.x, bx, by);
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
-    pass1_tile<T, RX, RY, KZ>(sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
+    pass1_tile<T, RX, RY, KZ>((int)threadIdx.x, sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
 }
 
 // W_xy = fl32(1/U_xy) off the diagonal, 0 on it (used after a split pass 1).
@@ -446,12 +460,11 @@ struct Pass2Out {
 // by every thread of a workgroup of Pass2Cfg::NT threads; `sm` points to
 // Pass2Cfg::LDS_VEC uint4 of LDS.
 template <int T, int RX, int KY, bool F64>
-__device__ __forceinline__ void pass2_tile(uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
+__device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            const float *__restrict__ W, int64_t ldw, Pass2Out out, int32_t bx,
                                            int32_t bz, int64_t ybeg, int64_t yend, bool vec_ok_d, bool vec_ok_w) {
     using Cfg = Pass2Cfg<T, RX, KY>;
     const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
-    const int tid = threadIdx.x;
     constexpr int RZ = Cfg::RZ;
     const int tx = tid % Cfg::TX, tz = tid / Cfg::TX;
 
@@ -644,7 +657,7 @@ __global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT), PALD_P2_MIN_WAVES) void 
     } else {
         out.slab = partial + (int64_t)blockIdx.y * n * n;
     }
-    pass2_tile<T, RX, KY, F64>(sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
+    pass2_tile<T, RX, KY, F64>((int)threadIdx.x, sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
 }
 
 // C_xz = fl32( sum_k partial[k][x][z] / (n-1) ), the only cross-tile reduction.

@@ -23,8 +23,12 @@ using namespace pald;
 using namespace pald_host;
 
 // ---- single-matrix tile configuration -------------------------------------
-// pass 1: 128 x 128 (x,y) tiles, 8 x 8 counters per thread, 16 z rows per stage
-constexpr int P1_T = 128, P1_RX = 8, P1_RY = 8, P1_KZ = 16;
+// pass 1: 128 x 128 (x,y) tiles, 4 x 8 counters per thread (512 threads, 4
+// waves per SIMD: 128 VGPRs), 16 z rows per stage
+#ifndef PALD_P1_RX
+#define PALD_P1_RX 4
+#endif
+constexpr int P1_T = 128, P1_RX = PALD_P1_RX, P1_RY = 8, P1_KZ = 16;
 using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
 // pass 2: symmetric 64 x 64 (x,z) tiles, P2_RX x 4 pairs (both directions) per thread,
 // 16 y rows per stage

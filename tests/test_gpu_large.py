@@ -13,7 +13,7 @@ from paper_2307_16652_amd import synth
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 N = 65536
-ORACLE_ROWS = 32
+ORACLE_ROWS = 64
 
 
 @pytest.fixture(scope="module", autouse=True)

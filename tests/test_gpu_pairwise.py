@@ -253,3 +253,53 @@ def test_diagonal_identity_without_coincident_points():
     np.fill_diagonal(Ud, np.inf)
     expect = (1.0 / Ud).sum(axis=1) / (400 - 1)
     np.testing.assert_allclose(np.diag(C).astype(np.float64), expect, rtol=1e-6, atol=0)
+
+
+def test_cohesion_captured_in_a_graph_replays_exactly():
+    """pald_cohesion enqueues kernels only (no allocation, no memset node), so it can
+    be captured; every replay, with eager work in between, equals the eager result."""
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    for n, opts in ((300, {}), (257, {"y_chunks": 3, "z_chunks": 2})):
+        D = to_gpu(synth.mixture8d(n=n, seed=40 + n))
+        ws = pald.workspace(n, D.device, **opts)
+        U = torch.empty((n, n), dtype=torch.int32, device="cuda")
+        C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        pald.cohesion(D, ws=ws, out_u=U, out_c=C, **opts)
+        torch.cuda.synchronize()
+        Ue, Ce = U.clone(), C.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            pald.cohesion(D, ws=ws, out_u=U, out_c=C, **opts)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            U.fill_(-1)
+            C.fill_(-1.0)
+            _ = (D * 2.0).sum()  # eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(U, Ue), f"n={n} replay {rep}: U differs"
+            assert torch.equal(C, Ce), f"n={n} replay {rep}: C differs"
+        del g
+
+
+def test_cohesion_on_a_side_stream():
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    D = synth.grid3d(n=260, seed=6)
+    Uo, Co = oracle.pald(D)
+    Dg = to_gpu(D)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        U, C = pald.cohesion(Dg)
+    s.synchronize()
+    assert_u_equal(U.cpu().numpy(), Uo, "side stream")
+    assert_c_close(C.cpu().numpy(), Co, what="side stream")

@@ -251,7 +251,7 @@ typedef struct pald_batch_plan pald_batch_plan;
  * larger than the last n_max use the last entry). */
 typedef struct pald_batch_bucket {
     int32_t n_max;
-    int32_t p1_tile;   /* pass-1 tile side: 64 (or 0 for the default, 64) */
+    int32_t tile;      /* pass-2 tile side: 64 or 32 (0 = 64); pass-1 tiles are 64 */
     int32_t y_chunks;  /* pass-2 split of the y range (1 = no split) */
     int32_t reserved;  /* must be zero */
 } pald_batch_bucket;

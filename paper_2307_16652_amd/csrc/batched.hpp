@@ -40,6 +40,7 @@ struct BatchMatrix {
     int32_t y_per_chunk;
     int32_t ctr2;      // index of its first per-tile arrival counter (y_chunks > 1)
     int32_t vec_d;     // rows of D start on 16-byte boundaries (given an aligned base)
+    int32_t tile2;     // pass-2 tile side (BATCH_P2_T or BATCH_P2S_T)
 };
 
 // A value every lane of the wave holds, moved to a scalar register (the item
@@ -76,10 +77,14 @@ constexpr int BATCH_P1_T = 64, BATCH_P1_RX = BATCH_THREADS == 256 ? 2 : 1;
 constexpr int BATCH_P2_T = 64, BATCH_P2_RX = BATCH_THREADS == 256 ? 4 : 2, BATCH_P2_KY = PALD_P2_KY;
 using BatchP1 = Pass1Cfg<BATCH_P1_T, BATCH_P1_RX, 8, 16>;
 using BatchP2 = Pass2Cfg<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY>;
-static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS,
-              "both batched tile shapes use one workgroup size");
+// The small pass-2 shape: 32 x 32 tiles, one x and four z per thread (less
+// padding and less duplicated work on diagonal tiles for mid-size matrices).
+constexpr int BATCH_P2S_T = 32, BATCH_P2S_RX = BATCH_THREADS == 256 ? 1 : 0;
+using BatchP2S = Pass2Cfg<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY>;
+static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS && BatchP2S::NT == BATCH_THREADS,
+              "all batched tile shapes use one workgroup size");
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int BATCH_LDS_VEC = cmax(BatchP1::LDS_VEC, BatchP2::LDS_VEC);
+constexpr int BATCH_LDS_VEC = cmax(BatchP1::LDS_VEC, cmax(BatchP2::LDS_VEC, BatchP2S::LDS_VEC));
 
 // Counter layout (uint32): [0] queue head, [1 .. count] pass-1 done counts,
 // [1 + count ..] per-tile arrival counters of split pass-2 tiles.
@@ -155,7 +160,8 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                 tri_tile(tile, bx, bz);
                 const int64_t ybeg = (int64_t)chunk * mypc;
                 const int64_t yend = min(n, ybeg + (int64_t)mypc);
-                constexpr int64_t TT2 = 2 * BATCH_P2_T * BATCH_P2_T;
+                const int32_t t2 = uniform_i32(s_m.tile2);
+                const int64_t TT2 = 2 * (int64_t)t2 * t2;
                 Pass2Out out{nullptr, 0, nullptr, nullptr};
                 if (mychunks == 1) {
                     out.C = C + moff;
@@ -163,8 +169,13 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                 } else {
                     out.tile = Pr + mpoff + ((int64_t)tile * mychunks + chunk) * TT2;
                 }
-                pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff, mldw,
-                                                                       out, bx, bz, ybeg, yend, vec_d, true);
+                if (t2 == BATCH_P2_T)
+                    pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, true>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff,
+                                                                           mldw, out, bx, bz, ybeg, yend, vec_d, true);
+                else
+                    pass2_tile<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY, false, true>(opaque_tid(), sm, D + moff, n, n,
+                                                                             Wr + mwoff, mldw, out, bx, bz, ybeg, yend,
+                                                                             vec_d, true);
                 if (mychunks > 1) {
                     __threadfence();
                     __syncthreads();
@@ -179,18 +190,20 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                         const int32_t chunks = mychunks;
                         int32_t tbx, tbz;
                         tri_tile(tile, tbx, tbz);
-                        const int64_t X0 = (int64_t)tbx * BATCH_P2_T, Z0 = (int64_t)tbz * BATCH_P2_T;
+                        const int32_t tt = uniform_i32(s_m.tile2);
+                        const int64_t TTr = 2 * (int64_t)tt * tt;
+                        const int64_t X0 = (int64_t)tbx * tt, Z0 = (int64_t)tbz * tt;
                         const double nm1 = (double)(n - 1);
-                        const double *tiles = Pr + mpoff + (int64_t)tile * chunks * TT2;
+                        const double *tiles = Pr + mpoff + (int64_t)tile * chunks * TTr;
                         float *Cm = C + moff;
-                        for (int e = tid; e < BATCH_P2_T * BATCH_P2_T; e += BATCH_THREADS) {
-                            const int i = e / BATCH_P2_T, j = e % BATCH_P2_T;
+                        for (int e = tid; e < tt * tt; e += BATCH_THREADS) {
+                            const int i = e / tt, j = e % tt;
                             const int64_t x = X0 + i, z = Z0 + j;
                             if (x >= n || z >= n) continue;
                             double sf = 0.0, sr = 0.0;
                             for (int32_t k = 0; k < chunks; ++k) {
-                                sf += tiles[k * TT2 + e];
-                                sr += tiles[k * TT2 + BATCH_P2_T * BATCH_P2_T + e];
+                                sf += tiles[k * TTr + e];
+                                sr += tiles[k * TTr + (int64_t)tt * tt + e];
                             }
                             Cm[x * n + z] = (float)(sf / nm1);
                             if (tbx != tbz) Cm[z * n + x] = (float)(sr / nm1);

@@ -100,14 +100,43 @@ __device__ __forceinline__ void focus_count8(int32_t (&c)[8], uint32_t x, const 
 // instructions after it is written (the wait states a vector read of a
 // vector-written scalar register needs) and the four pairs interleave; the
 // compiler's own schedule funnels the masks through one or two registers.
+// FEW_SGPR: the two select masks of a pair rotate through two register sets,
+// so a block holds 8 scalar-register pairs of masks instead of 12 (for
+// kernels short of scalar registers); the default keeps all 12 live.
 // Registers only, no memory access; EXEC is back to its entry value at exit.
+template <bool FEW_SGPR>
 __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], const uint32_t (&t)[4], uint32_t a,
                                                 const uint32_t (&b)[4], float wx, float whx, const float (&wz)[4],
                                                 const float (&whz)[4]) {
     uint32_t m0, m1, m2, m3;
     float f0, f1, f2, f3, g0, g1, g2, g3;
-    uint64_t i0, i1, i2, i3, p0, p1, p2, p3, q0, q1, q2, q3;
-#define PALD_T4_HEAD                                                                                            \
+    uint64_t i0, i1, i2, i3, p[4], q[4];
+#define PALD_T4_HEAD_ROT                                                                                            \
+    "v_min_u32 %[m0], %[a], %[b0]\n\t"                                                                          \
+    "v_min_u32 %[m1], %[a], %[b1]\n\t"                                                                          \
+    "v_min_u32 %[m2], %[a], %[b2]\n\t"                                                                          \
+    "v_min_u32 %[m3], %[a], %[b3]\n\t"                                                                          \
+    "v_cmp_le_u32_e64 %[i0], %[t0], %[m0]\n\t"                                                                  \
+    "v_cmp_le_u32_e64 %[i1], %[t1], %[m1]\n\t"                                                                  \
+    "v_cmp_le_u32_e64 %[i2], %[t2], %[m2]\n\t"                                                                  \
+    "v_cmp_le_u32_e64 %[i3], %[t3], %[m3]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[pa], %[t0], %[b0]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[qa], %[t0], %[a]\n\t"                                                                   \
+    "v_cmp_lt_u32_e64 %[pb], %[t1], %[b1]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[qb], %[t1], %[a]\n\t"                                                                   \
+    "v_cndmask_b32_e64 %[f0], %[whx], %[wx], %[pa]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g0], %[whz0], %[wz0], %[qa]\n\t"                                                       \
+    "v_cmp_lt_u32_e64 %[pa], %[t2], %[b2]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[qa], %[t2], %[a]\n\t"                                                                   \
+    "v_cndmask_b32_e64 %[f1], %[whx], %[wx], %[pb]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g1], %[whz1], %[wz1], %[qb]\n\t"                                                       \
+    "v_cmp_lt_u32_e64 %[pb], %[t3], %[b3]\n\t"                                                                  \
+    "v_cmp_lt_u32_e64 %[qb], %[t3], %[a]\n\t"                                                                   \
+    "v_cndmask_b32_e64 %[f2], %[whx], %[wx], %[pa]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g2], %[whz2], %[wz2], %[qa]\n\t"                                                       \
+    "v_cndmask_b32_e64 %[f3], %[whx], %[wx], %[pb]\n\t"                                                         \
+    "v_cndmask_b32_e64 %[g3], %[whz3], %[wz3], %[qb]\n\t"
+#define PALD_T4_HEAD_WIDE                                                                                       \
     "v_min_u32 %[m0], %[a], %[b0]\n\t"                                                                          \
     "v_min_u32 %[m1], %[a], %[b1]\n\t"                                                                          \
     "v_min_u32 %[m2], %[a], %[b2]\n\t"                                                                          \
@@ -135,8 +164,11 @@ __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], 
 #define PALD_T4_OPERANDS                                                                                        \
     [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3), [f0] "=&v"(f0), [f1] "=&v"(f1),          \
         [f2] "=&v"(f2), [f3] "=&v"(f3), [g0] "=&v"(g0), [g1] "=&v"(g1), [g2] "=&v"(g2), [g3] "=&v"(g3),       \
-        [i0] "=&s"(i0), [i1] "=&s"(i1), [i2] "=&s"(i2), [i3] "=&s"(i3), [p0] "=&s"(p0), [p1] "=&s"(p1),       \
-        [p2] "=&s"(p2), [p3] "=&s"(p3), [q0] "=&s"(q0), [q1] "=&s"(q1), [q2] "=&s"(q2), [q3] "=&s"(q3)
+        [i0] "=&s"(i0), [i1] "=&s"(i1), [i2] "=&s"(i2), [i3] "=&s"(i3)
+#define PALD_T4_MASKS_ROT [pa] "=&s"(p[0]), [pb] "=&s"(p[1]), [qa] "=&s"(q[0]), [qb] "=&s"(q[1])
+#define PALD_T4_MASKS_WIDE                                                                                      \
+    [p0] "=&s"(p[0]), [p1] "=&s"(p[1]), [p2] "=&s"(p[2]), [p3] "=&s"(p[3]), [q0] "=&s"(q[0]), [q1] "=&s"(q[1]), \
+        [q2] "=&s"(q[2]), [q3] "=&s"(q[3])
 #define PALD_T4_INPUTS                                                                                          \
     [t0] "v"(t[0]), [t1] "v"(t[1]), [t2] "v"(t[2]), [t3] "v"(t[3]), [a] "v"(a), [b0] "v"(b[0]),               \
         [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3]), [wx] "v"(wx), [whx] "v"(whx), [wz0] "v"(wz[0]),       \
@@ -147,26 +179,49 @@ __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], 
         // each pair's membership mask in turn and restored at the end, which
         // spares the select-with-zero of every term.
         uint64_t sv;
-        asm(PALD_T4_HEAD
-            "s_and_saveexec_b64 %[sv], %[i0]\n\t"
-            "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
-            "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
-            "s_and_b64 exec, %[sv], %[i1]\n\t"
-            "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
-            "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
-            "s_and_b64 exec, %[sv], %[i2]\n\t"
-            "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
-            "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
-            "s_and_b64 exec, %[sv], %[i3]\n\t"
-            "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
-            "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
-            "s_mov_b64 exec, %[sv]"
-            : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
-              [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS
-            : PALD_T4_INPUTS
-            : "scc");
+        if (FEW_SGPR)
+            asm(PALD_T4_HEAD_ROT
+                "s_and_saveexec_b64 %[sv], %[i0]\n\t"
+                "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
+                "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
+                "s_and_b64 exec, %[sv], %[i1]\n\t"
+                "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
+                "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
+                "s_and_b64 exec, %[sv], %[i2]\n\t"
+                "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
+                "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
+                "s_and_b64 exec, %[sv], %[i3]\n\t"
+                "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
+                "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
+                "s_mov_b64 exec, %[sv]"
+                : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
+                  [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS, PALD_T4_MASKS_ROT
+                : PALD_T4_INPUTS
+                : "scc");
+        else
+            asm(PALD_T4_HEAD_WIDE
+                "s_and_saveexec_b64 %[sv], %[i0]\n\t"
+                "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
+                "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
+                "s_and_b64 exec, %[sv], %[i1]\n\t"
+                "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
+                "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
+                "s_and_b64 exec, %[sv], %[i2]\n\t"
+                "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
+                "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
+                "s_and_b64 exec, %[sv], %[i3]\n\t"
+                "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
+                "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
+                "s_mov_b64 exec, %[sv]"
+                : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
+                  [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS, PALD_T4_MASKS_WIDE
+                : PALD_T4_INPUTS
+                : "scc");
     }
-#undef PALD_T4_HEAD
+#undef PALD_T4_HEAD_ROT
+#undef PALD_T4_HEAD_WIDE
+#undef PALD_T4_MASKS_ROT
+#undef PALD_T4_MASKS_WIDE
 #undef PALD_T4_OPERANDS
 #undef PALD_T4_INPUTS
 }
@@ -436,10 +491,10 @@ struct Pass2Cfg {
     static constexpr int ROW = 4 * T;                   // loaded per y: a | W_yx | b | W_yz
     static constexpr int LDS_ROW = 6 * T;               // staged per y: ... | W_yx/2 | W_yz/2
     static constexpr int VEC_PER_CHUNK = KY * ROW / 4;
-    static constexpr int VEC_PER_THREAD = VEC_PER_CHUNK / NT;
+    static constexpr int VEC_PER_THREAD = (VEC_PER_CHUNK + NT - 1) / NT;  // the last round may be partial
+    static constexpr bool VEC_EVEN = VEC_PER_CHUNK % NT == 0;
     static constexpr int LDS_VEC = 2 * KY * LDS_ROW / 4; // uint4 of LDS, double-buffered
     static constexpr int RUN = PALD_P2_RUN;             // float32 run length before a Kahan fold
-    static_assert(VEC_PER_CHUNK % NT == 0, "chunk must split evenly over threads");
     static_assert(KY % RUN == 0, "KY must be a multiple of the run length");
     static_assert(T % 4 == 0, "tile side must be a multiple of 4");
 };
@@ -459,7 +514,7 @@ struct Pass2Out {
 // One pass-2 tile (bx, bz), bx <= bz, over the y range [ybeg, yend).  Called
 // by every thread of a workgroup of Pass2Cfg::NT threads; `sm` points to
 // Pass2Cfg::LDS_VEC uint4 of LDS.
-template <int T, int RX, int KY, bool F64>
+template <int T, int RX, int KY, bool F64, bool FEW_SGPR = false>
 __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            const float *__restrict__ W, int64_t ldw, Pass2Out out, int32_t bx,
                                            int32_t bz, int64_t ybeg, int64_t yend, bool vec_ok_d, bool vec_ok_w) {
@@ -501,6 +556,7 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
 #pragma unroll
         for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) {
             const int v = tid + k * Cfg::NT;
+            if (!Cfg::VEC_EVEN && v >= Cfg::VEC_PER_CHUNK) break;
             const int r = v / (Cfg::ROW / 4);
             const int g = v % (Cfg::ROW / 4);
             const int seg = g / (T / 4);           // 0: D x-range, 1: W x-range, 2: D z-range, 3: W z-range
@@ -516,6 +572,7 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
 #pragma unroll
         for (int k = 0; k < Cfg::VEC_PER_THREAD; ++k) {
             const int v = tid + k * Cfg::NT;
+            if (!Cfg::VEC_EVEN && v >= Cfg::VEC_PER_CHUNK) break;
             const int r = v / (Cfg::ROW / 4);
             const int g = v % (Cfg::ROW / 4);
             const int seg = g / (T / 4);
@@ -590,7 +647,7 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
                     load_row(y0 + yy, av, wx, whx, bv, wz, whz);
 #pragma unroll
                     for (int i = 0; i < RX; ++i)
-                        cohesion_terms4(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                        cohesion_terms4<FEW_SGPR>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
                 }
                 // Kahan fold of the finished runs (r = run - c): s + r, with the
                 // new negated compensation -c = r - ((s + r) - s) left in r.

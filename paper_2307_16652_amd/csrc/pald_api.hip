@@ -407,7 +407,8 @@ pald_status check_config(const pald_batch_config *cfg) {
         return PALD_ERR_ARG;
     for (int b = 0; b < cfg->nbuckets; ++b) {
         const pald_batch_bucket &k = cfg->bucket[b];
-        if ((k.p1_tile != 0 && k.p1_tile != BATCH_P1_T) || k.y_chunks < 1 || k.n_max < 2 || k.reserved != 0)
+        if ((k.tile != 0 && k.tile != BATCH_P2_T && k.tile != BATCH_P2S_T) || k.y_chunks < 1 || k.n_max < 2 ||
+            k.reserved != 0)
             return PALD_ERR_ARG;
         if (b > 0 && k.n_max <= cfg->bucket[b - 1].n_max) return PALD_ERR_ARG;
     }
@@ -436,7 +437,6 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
     L.n.assign(n_host, n_host + count);
     L.off.resize(count);
     int64_t off = 0, woff = 0, poff = 0, ctr2 = 0;
-    constexpr int64_t T2 = BATCH_P2_T;
     for (int32_t i = 0; i < count; ++i) {
         const int64_t n = n_host[i];
         if (n < 2 || n > (1 << 20)) return PALD_ERR_ARG;
@@ -449,6 +449,8 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
         m.woff = woff;
         const int64_t nb1 = ceil_div(n, BATCH_P1_T);
         m.tiles1 = (int32_t)(nb1 * (nb1 + 1) / 2);
+        const int64_t T2 = bk.tile ? bk.tile : BATCH_P2_T;
+        m.tile2 = (int32_t)T2;
         const int64_t nb2 = ceil_div(n, T2);
         const int64_t tiles2 = nb2 * (nb2 + 1) / 2;
         int64_t yc = std::max<int64_t>(1, std::min<int64_t>(bk.y_chunks, ceil_div(n, BATCH_P2_KY)));
@@ -477,7 +479,7 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
 
     auto emit_p2 = [&](int32_t i) {
         const BatchMatrix &m = L.mats[i];
-        const int64_t nb2 = ceil_div(m.n, T2);
+        const int64_t nb2 = ceil_div(m.n, m.tile2);
         const int64_t tiles2 = nb2 * (nb2 + 1) / 2;
         for (int64_t t = 0; t < tiles2; ++t)
             for (int32_t c = 0; c < m.y_chunks; ++c) L.items.push_back(make_int4(i, ITEM_PASS2, (int)t, c));

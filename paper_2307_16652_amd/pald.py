@@ -60,7 +60,7 @@ class Options(ctypes.Structure):
 
 
 class BatchBucket(ctypes.Structure):
-    _fields_ = [("n_max", ctypes.c_int32), ("p1_tile", ctypes.c_int32),
+    _fields_ = [("n_max", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("y_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -72,7 +72,8 @@ class BatchConfig(ctypes.Structure):
 
 def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int = 0,
                       timestamps: bool = False) -> BatchConfig:
-    """buckets: list of (n_max, y_chunks) or dicts with keys n_max / y_chunks (p1_tile optional)."""
+    """buckets: list of (n_max, y_chunks) or (n_max, y_chunks, tile) tuples, or dicts with keys
+    n_max / y_chunks / tile (tile = pass-2 tile side, 64 or 32; default 64)."""
     c = BatchConfig()
     buckets = list(buckets or [])
     if len(buckets) > BATCH_MAX_BUCKETS:
@@ -80,10 +81,12 @@ def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int =
     for i, b in enumerate(buckets):
         if isinstance(b, dict):
             c.bucket[i].n_max = int(b["n_max"])
-            c.bucket[i].p1_tile = int(b.get("p1_tile", 0))
+            c.bucket[i].tile = int(b.get("tile", 0))
             c.bucket[i].y_chunks = int(b.get("y_chunks", 1))
         else:
             c.bucket[i].n_max, c.bucket[i].y_chunks = int(b[0]), int(b[1])
+            if len(b) > 2:
+                c.bucket[i].tile = int(b[2])
     c.nbuckets = len(buckets)
     c.workgroups_per_cu = int(workgroups_per_cu)
     c.queue_lag = int(queue_lag)

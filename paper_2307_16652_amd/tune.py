@@ -6,6 +6,9 @@
 Searches, on the 2000-matrix batch (n uniform in [32, 1024], 2-5 Gaussian
 clusters in R^4), for
 
+* the pass-2 tile side of each size bucket (64 or 32: the smaller tile pads
+  less and repeats less work on diagonal tiles, the larger one reuses each
+  staged row over more pairs),
 * the pass-2 y-split depth of each size bucket (splitting a large matrix's
   pass-2 tiles over y shortens the items at the end of the queue),
 * the persistent grid size (workgroups per CU), and
@@ -14,8 +17,8 @@ clusters in R^4), for
 by coordinate descent on the measured time of one whole batched launch
 (median of `reps` graph replays), and writes the winner to
 tuning/batch_gfx950.json, which `pald.load_tuning()` (and so `bench.py`)
-picks up.  The tile shapes of the batched kernel are fixed at build time by
-its register budget; they are not part of this search.
+picks up.  Both tile shapes are compiled into the batched kernel; the search
+picks one per bucket.
 
 With --variants it instead times the pairwise, hybrid (triplet pass 1 +
 pairwise pass 2) and triplet variants of the single-matrix path on Gaussian
@@ -34,6 +37,7 @@ import numpy as np
 
 BUCKETS = (128, 256, 512, 1 << 30)
 Y_CHUNKS = (1, 2, 3, 4)
+TILES = (64, 32)
 LAGS = (1, 2, 4, 8)
 WPC = (1, 2)
 
@@ -88,8 +92,10 @@ class Batch:
             plan.close()
 
 
-def config_of(pald, chunks, wpc, lag):
-    return pald.make_batch_config([(b, c) for b, c in zip(BUCKETS, chunks)], workgroups_per_cu=wpc, queue_lag=lag)
+def config_of(pald, chunks, wpc, lag, tiles=None):
+    tiles = tiles or [64] * len(BUCKETS)
+    return pald.make_batch_config([(b, c, t) for b, c, t in zip(BUCKETS, chunks, tiles)], workgroups_per_cu=wpc,
+                                  queue_lag=lag)
 
 
 def tune(reps: int = 3, out: str | None = None) -> dict:
@@ -101,33 +107,39 @@ def tune(reps: int = 3, out: str | None = None) -> dict:
     dev = torch.device("cuda:0")
     batch = Batch(dev)
     chunks = [1] * len(BUCKETS)
+    tiles = [64] * len(BUCKETS)
     wpc, lag = 0, 0
-    best = batch.time(config_of(pald, chunks, wpc, lag), reps)
+    best = batch.time(config_of(pald, chunks, wpc, lag, tiles), reps)
     log(f"defaults: {best:.3f} ms")
-    trials = [{"chunks": list(chunks), "wpc": wpc, "lag": lag, "ms": best}]
+    trials = [{"chunks": list(chunks), "tiles": list(tiles), "wpc": wpc, "lag": lag, "ms": best}]
 
-    def consider(c, w, l):
-        nonlocal best, chunks, wpc, lag
-        ms = batch.time(config_of(pald, c, w, l), reps)
-        trials.append({"chunks": list(c), "wpc": w, "lag": l, "ms": ms})
-        log(f"chunks={c} wpc={w} lag={l}: {ms:.3f} ms")
+    def consider(c, t, w, l):
+        nonlocal best, chunks, tiles, wpc, lag
+        ms = batch.time(config_of(pald, c, w, l, t), reps)
+        trials.append({"chunks": list(c), "tiles": list(t), "wpc": w, "lag": l, "ms": ms})
+        log(f"chunks={c} tiles={t} wpc={w} lag={l}: {ms:.3f} ms")
         if ms < best * 0.995:
-            best, chunks, wpc, lag = ms, list(c), w, l
+            best, chunks, tiles, wpc, lag = ms, list(c), list(t), w, l
 
     for w in WPC:
         for l in LAGS:
-            consider(chunks, w, l)
+            consider(chunks, tiles, w, l)
     for _ in range(2):  # two sweeps of coordinate descent over the buckets
         for b in reversed(range(len(BUCKETS))):
+            for tl in TILES:
+                if tl != tiles[b]:
+                    cand = list(tiles)
+                    cand[b] = tl
+                    consider(chunks, cand, wpc, lag)
             for c in Y_CHUNKS:
                 if c != chunks[b]:
                     cand = list(chunks)
                     cand[b] = c
-                    consider(cand, wpc, lag)
+                    consider(cand, tiles, wpc, lag)
     result = {
         "arch": "gfx950",
         "workload": "2000 matrices, n uniform in [32, 1024], 2-5 Gaussian clusters in R^4, seed 4",
-        "buckets": [{"n_max": b, "y_chunks": c} for b, c in zip(BUCKETS, chunks)],
+        "buckets": [{"n_max": b, "y_chunks": c, "tile": t} for b, c, t in zip(BUCKETS, chunks, tiles)],
         "workgroups_per_cu": wpc,
         "queue_lag": lag,
         "ms_per_batch": round(best, 3),

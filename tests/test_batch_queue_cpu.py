@@ -112,6 +112,24 @@ def test_model_detects_a_bad_queue():
         simulate(bad, tiles1, 1, np.random.default_rng(0))
 
 
+@pytest.mark.parametrize("tile", [32, 64])
+def test_pass2_tile_side_per_bucket(tile):
+    sizes = [2, 31, 32, 33, 100, 300, 1000]
+    cfg = pald.make_batch_config([(64, 1, 32), (1 << 30, 2, tile)])
+    items, tiles1 = pald.batch_queue(sizes, grid=16, config=cfg)
+    for m, n in enumerate(sizes):
+        t2, ch = (32, 1) if n <= 64 else (tile, 2)
+        nb1, nb2 = -(-n // 64), -(-n // t2)
+        assert tiles1[m] == nb1 * (nb1 + 1) // 2  # pass-1 tiles stay 64 wide
+        mine = items[(items[:, 0] == m) & (items[:, 1] == 1)]
+        ch = min(ch, -(-n // 12))
+        assert len(mine) == nb2 * (nb2 + 1) // 2 * len(set(mine[:, 3].tolist()))
+        assert mine[:, 2].max() == nb2 * (nb2 + 1) // 2 - 1
+    rng = np.random.default_rng(3)
+    _, ran = simulate(items, tiles1, 5, rng)
+    assert ran == len(items)
+
+
 def test_y_split_items():
     cfg = pald.make_batch_config([(100, 1), (1 << 30, 4)])
     items, _ = pald.batch_queue([90, 300], grid=8, config=cfg)
@@ -132,6 +150,9 @@ def test_bad_batch_arguments():
     with pytest.raises(pald.PaldError):
         pald.batch_queue([10], grid=4, config=bad)
     bad = pald.make_batch_config([(100, 0)])
+    with pytest.raises(pald.PaldError):
+        pald.batch_queue([10], grid=4, config=bad)
+    bad = pald.make_batch_config([(100, 1, 48)])  # only 64- and 32-wide pass-2 tiles exist
     with pytest.raises(pald.PaldError):
         pald.batch_queue([10], grid=4, config=bad)
 

@@ -85,6 +85,28 @@ def test_y_split_tiles(chunks):
     check_all(mats, Us, Cs, what=f"y_chunks={chunks}")
 
 
+@pytest.mark.parametrize("chunks", [1, 3])
+def test_small_pass2_tiles(chunks):
+    """The 32-wide pass-2 tile (chosen per size bucket): oracle parity on ragged and
+    tie-heavy sizes, with and without a y split, and C bit-identical to the 64-wide
+    tile (each C entry is summed over y in the same order by both shapes)."""
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch(RAGGED, seed=11) + make_batch([40, 96, 161], seed=12, kind="grid")
+    small = pald.make_batch_config([(1 << 30, chunks, 32)])
+    mixed = pald.make_batch_config([(100, chunks, 32), (1 << 30, chunks, 64)])
+    wide = pald.make_batch_config([(1 << 30, chunks, 64)])
+    log(f"[batched] 32-wide pass-2 tiles, y_chunks={chunks}")
+    _, _, Us, Cs = run_batch(mats, config=small)
+    check_all(mats, Us, Cs, what=f"tile 32 y_chunks={chunks}")
+    _, _, Um, Cm = run_batch(mats, config=mixed)
+    _, _, Uw, Cw = run_batch(mats, config=wide)
+    for i in range(len(mats)):
+        assert np.array_equal(Us[i], Uw[i]) and np.array_equal(Um[i], Uw[i])
+        assert np.array_equal(Cs[i].view(np.int32), Cw[i].view(np.int32)), f"matrix {i}: tile 32 != tile 64"
+        assert np.array_equal(Cm[i].view(np.int32), Cw[i].view(np.int32))
+
+
 @pytest.mark.parametrize("wpc,lag", [(1, 1), (2, 5), (4, 1)])
 def test_grid_and_lag_settings(wpc, lag):
     from paper_2307_16652_amd import pald

@@ -48,7 +48,7 @@ constexpr int TRI_T = 64;         // owner tile side
 constexpr int TRI_R = 4;          // 4 x 4 (p, r) per thread
 constexpr int TRI_KQ = 16;        // q rows per LDS stage
 constexpr int TRI_THREADS = 256;  // tid = tx * 16 + tz; p = X0 + 4 tx + i, r = Z0 + 4 tz + j
-constexpr int TRI_RUN = 8;        // float32 run length of the (p, r) sums before a float64 fold
+constexpr int TRI_RUN = 8;        // float32 run length of the (p, r) sums before a Kahan fold
 
 // U_xy = 2 off the diagonal, U_xx = #{z : d_xz <= 0}.
 __global__ void triplet_init_u_kernel(const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U,
@@ -126,7 +126,7 @@ __device__ __forceinline__ V wave_rows_sum(V v) {
 // One owner tile of either pass.  PASS2 = false: focus sizes into U (int32,
 // atomics); PASS2 = true: cohesion sums into A (float64, atomics).
 template <bool PASS2>
-__global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__restrict__ D, int64_t n, int64_t ldd,
+__global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__restrict__ D, int64_t n, int64_t ldd,
                                                               const float *__restrict__ W, int64_t ldw,
                                                               int32_t *__restrict__ U, int64_t ldu,
                                                               double *__restrict__ A, int32_t vec_d, int32_t vec_w,
@@ -148,36 +148,33 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
     const int tx = tid / 16, tz = tid % 16, wave = tid / 64, row = (tid % 64) / 16;
     const bool diag_owner = bx == bz;
 
-    int64_t p[R], r[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        p[i] = X0 + tx * R + i;
-        r[i] = Z0 + tz * R + i;
-    }
+    // p_i = X0 + 4 tx + i, r_j = Z0 + 4 tz + j (recomputed where used: no
+    // registers held for them across the q loop)
+    auto p = [&](int i) { return X0 + tx * R + i; };
+    auto r = [&](int j) { return Z0 + tz * R + j; };
     // stationary (p, r) data
     uint32_t b[R][R];
-    float wpr[R][R], whpr[R][R];
+    float wpr[R][R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const bool in = p[i] < n && r[j] < n;
-            b[i][j] = in ? key_of(D[p[i] * ldd + r[j]]) : 0u;
-            const float w = (PASS2 && in) ? W[p[i] * ldw + r[j]] : 0.0f;
+            const bool in = p(i) < n && r(j) < n;
+            b[i][j] = in ? key_of(D[p(i) * ldd + r(j)]) : 0u;
+            const float w = (PASS2 && in) ? W[p(i) * ldw + r(j)] : 0.0f;
             wpr[i][j] = w;
-            whpr[i][j] = 0.5f * w;
         }
-    // (p, r) accumulators
+    // (p, r) accumulators: float32 runs r and Kahan sums s (a run starts from
+    // the negated compensation of the previous fold, as in the pairwise pass 2)
     int32_t upr[R][R];
-    float rpr[R][R], rrp[R][R];
-    double spr[R][R], srp[R][R];
+    float rpr[R][R], rrp[R][R], spr[R][R], srp[R][R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             upr[i][j] = 0;
             rpr[i][j] = rrp[i][j] = 0.0f;
-            spr[i][j] = srp[i][j] = 0.0;
+            spr[i][j] = srp[i][j] = 0.0f;
         }
 
     // the middle index runs over [X0, min(n, Z0 + T)); triples outside p < q < r
@@ -235,6 +232,7 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
         const int64_t qc = qlo + st * KQ;
         if (st + 1 < nst) fetch(qc + KQ);
         const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (KQ * LDS_ROW / 4));
+#pragma unroll 1
         for (int qq = 0; qq < KQ; ++qq) {
             const int64_t q = qc + qq;
             const uint32_t *rowp = s + qq * LDS_ROW;
@@ -254,8 +252,8 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
             uint64_t vp[R], vr[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                vp[i] = lane_mask(p[i] < q);
-                vr[i] = lane_mask(q < r[i] && r[i] < n);
+                vp[i] = lane_mask(p(i) < q);
+                vr[i] = lane_mask(q < r(i) && r(i) < n);
             }
             Part tpq[R], tqp[R], tqr[R], trq[R];
 #pragma unroll
@@ -276,8 +274,9 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
                     } else {
                         const float t1 = lane_bit(eb) ? (lane_bit(ec) ? whpq[i] : wpq[i]) : 0.0f;  // c_pr
                         const float t2 = lane_bit(ec) ? (lane_bit(eb) ? whpq[i] : wpq[i]) : 0.0f;  // c_qr
-                        const float t3 = lane_bit(ea) ? (lane_bit(ec) ? whpr[i][j] : wpr[i][j]) : 0.0f;  // c_pq
-                        const float t4 = lane_bit(ec) ? (lane_bit(ea) ? whpr[i][j] : wpr[i][j]) : 0.0f;  // c_rq
+                        const float whpr = 0.5f * wpr[i][j];  // exact; not kept across q
+                        const float t3 = lane_bit(ea) ? (lane_bit(ec) ? whpr : wpr[i][j]) : 0.0f;  // c_pq
+                        const float t4 = lane_bit(ec) ? (lane_bit(ea) ? whpr : wpr[i][j]) : 0.0f;  // c_rq
                         const float t5 = lane_bit(ea) ? (lane_bit(eb) ? whqr[j] : wqr[j]) : 0.0f;  // c_qp
                         const float t6 = lane_bit(eb) ? (lane_bit(ea) ? whqr[j] : wqr[j]) : 0.0f;  // c_rp
                         rpr[i][j] += t1;
@@ -293,9 +292,12 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
                 for (int i = 0; i < R; ++i)
 #pragma unroll
                     for (int j = 0; j < R; ++j) {
-                        spr[i][j] += (double)rpr[i][j];
-                        srp[i][j] += (double)rrp[i][j];
-                        rpr[i][j] = rrp[i][j] = 0.0f;
+                        float tk = spr[i][j] + rpr[i][j];
+                        rpr[i][j] = rpr[i][j] - (tk - spr[i][j]);
+                        spr[i][j] = tk;
+                        tk = srp[i][j] + rrp[i][j];
+                        rrp[i][j] = rrp[i][j] - (tk - srp[i][j]);
+                        srp[i][j] = tk;
                     }
             }
             // (p, q) and (q, p): sum over the 16 lanes sharing p; lane tz = k emits value k
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
 #pragma unroll
                     for (int i = 1; i < R; ++i)
                         if (tz == i) v = tpq[i];
-                    const int64_t pi = p[tz];
+                    const int64_t pi = p(tz);
                     if (pi < n && v != (Part)0) {
                         if (PASS2) {
                             unsafeAtomicAdd(&A[pi * n + q], (double)v);
@@ -324,7 +326,7 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
 #pragma unroll
                     for (int i = 1; i < R; ++i)
                         if (tz - R == i) v = tqp[i];
-                    const int64_t pi = p[tz - R];
+                    const int64_t pi = p(tz - R);
                     if (pi < n && v != (Part)0) unsafeAtomicAdd(&A[q * n + pi], (double)v);
                 }
             }
@@ -368,15 +370,15 @@ __global__ __launch_bounds__(TRI_THREADS) void triplet_kernel(const float *__res
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            if (p[i] >= n || r[j] >= n || (diag_owner && p[i] >= r[j])) continue;
+            if (p(i) >= n || r(j) >= n || (diag_owner && p(i) >= r(j))) continue;
             if (PASS2) {
-                const double f = spr[i][j] + (double)rpr[i][j];
-                const double g = srp[i][j] + (double)rrp[i][j];
-                if (f != 0.0) unsafeAtomicAdd(&A[p[i] * n + r[j]], f);
-                if (g != 0.0) unsafeAtomicAdd(&A[r[j] * n + p[i]], g);
+                const double f = (double)spr[i][j] + (double)rpr[i][j];
+                const double g = (double)srp[i][j] + (double)rrp[i][j];
+                if (f != 0.0) unsafeAtomicAdd(&A[p(i) * n + r(j)], f);
+                if (g != 0.0) unsafeAtomicAdd(&A[r(j) * n + p(i)], g);
             } else if (upr[i][j] != 0) {
-                atomicAdd(&U[p[i] * ldu + r[j]], upr[i][j]);
-                atomicAdd(&U[r[j] * ldu + p[i]], upr[i][j]);
+                atomicAdd(&U[p(i) * ldu + r(j)], upr[i][j]);
+                atomicAdd(&U[r(j) * ldu + p(i)], upr[i][j]);
             }
         }
 }

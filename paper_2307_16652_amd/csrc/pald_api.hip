@@ -224,7 +224,12 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
         triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0, (int32_t)t0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
-    return PALD_OK;
+    // the upper triangle holds U; mirror it
+    const int64_t nb32 = ceil_div(n, 32);
+    const int64_t mtiles = nb32 * (nb32 + 1) / 2;
+    if (mtiles > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    triplet_mirror_u_kernel<<<(unsigned)std::min<int64_t>(mtiles, 65536), 256, 0, s>>>(U, ldu, n, (int32_t)mtiles);
+    return launch_status();
 }
 
 pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,

@@ -25,7 +25,8 @@
 // shuffles), and added to the float64 accumulator with one atomic per value;
 // the (q, r) terms are summed over the wave's p with shuffles, then over the
 // four waves through LDS.  Every pair's terms come from several owners, so the
-// global sums use float64 atomics (C) and int32 atomics (U): U stays exact;
+// global sums use float64 atomics (C) and int32 atomics on the upper triangle
+// of U (mirrored to the lower one after the pass): U stays exact;
 // C is accurate to the same bound as the pairwise path but its last float64
 // bits depend on the order of the atomic adds, so it is not bitwise
 // reproducible run to run.
@@ -94,6 +95,38 @@ __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, in
             __syncthreads();
         }
         if (threadIdx.x == 0) A[x * n + x] = red[0];
+        __syncthreads();
+    }
+}
+
+// Pass 1 accumulates only the upper triangle of U (every triple adds to
+// U[lo][hi], lo < hi); this copies it to the lower triangle: U[y][x] = U[x][y]
+// for x < y.  32 x 32 tiles transposed through LDS; tile (ty, tx) with ty > tx
+// reads tile (tx, ty), diagonal tiles mirror within themselves.
+__global__ __launch_bounds__(256) void triplet_mirror_u_kernel(int32_t *__restrict__ U, int64_t ldu, int64_t n,
+                                                               int32_t tiles) {
+    __shared__ int32_t t[32][33];
+    const int64_t nb = (n + 31) / 32;
+    for (int64_t k = blockIdx.x; k < (int64_t)tiles; k += gridDim.x) {
+        // k enumerates the lower-triangle tiles (ty >= tx) row by row
+        int64_t ty = (int64_t)((sqrt(8.0 * (double)k + 1.0) - 1.0) * 0.5);
+        if (ty * (ty + 1) / 2 > k) --ty;
+        if ((ty + 1) * (ty + 2) / 2 <= k) ++ty;
+        const int64_t tx = k - ty * (ty + 1) / 2;
+        if (ty >= nb) break;
+        // load source tile (tx, ty): rows tx*32.., columns ty*32..
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int i = e / 32, j = e % 32;
+            const int64_t row = tx * 32 + i, col = ty * 32 + j;
+            t[i][j] = (row < n && col < n) ? U[row * ldu + col] : 0;
+        }
+        __syncthreads();
+        // write destination tile (ty, tx): U[ty*32 + j][tx*32 + i] = t[i][j] where row < col in the source
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int j = e / 32, i = e % 32;
+            const int64_t srow = tx * 32 + i, scol = ty * 32 + j;
+            if (srow < n && scol < n && srow < scol) U[scol * ldu + srow] = t[i][j];
+        }
         __syncthreads();
     }
 }
@@ -317,8 +350,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
                         if (PASS2) {
                             unsafeAtomicAdd(&A[pi * n + q], (double)v);
                         } else {
-                            atomicAdd(&U[pi * ldu + q], (int32_t)v);
-                            atomicAdd(&U[q * ldu + pi], (int32_t)v);
+                            atomicAdd(&U[pi * ldu + q], (int32_t)v);  // p < q: upper triangle only
                         }
                     }
                 } else if (PASS2 && tz < 2 * R) {
@@ -358,8 +390,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
             if (PASS2) {
                 unsafeAtomicAdd(d == 0 ? &A[q * n + rr] : &A[rr * n + q], (double)v);
             } else {
-                atomicAdd(&U[q * ldu + rr], (int32_t)v);
-                atomicAdd(&U[rr * ldu + q], (int32_t)v);
+                atomicAdd(&U[q * ldu + rr], (int32_t)v);  // q < r: upper triangle only
             }
         }
         __syncthreads();
@@ -377,8 +408,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
                 if (f != 0.0) unsafeAtomicAdd(&A[p(i) * n + r(j)], f);
                 if (g != 0.0) unsafeAtomicAdd(&A[r(j) * n + p(i)], g);
             } else if (upr[i][j] != 0) {
-                atomicAdd(&U[p(i) * ldu + r(j)], upr[i][j]);
-                atomicAdd(&U[r(j) * ldu + p(i)], upr[i][j]);
+                atomicAdd(&U[p(i) * ldu + r(j)], upr[i][j]);  // p < r: upper triangle only
             }
         }
 }

@@ -10,6 +10,18 @@ import numpy as np
 C_RTOL = 1e-6
 
 
+_ORACLE_CACHE = {}
+
+
+def oracle_full_cached(name: str, D: np.ndarray):
+    """Full oracle (U, C) of a named workload matrix, computed once per test session."""
+    import oracle
+
+    if name not in _ORACLE_CACHE:
+        _ORACLE_CACHE[name] = oracle.pald(D)
+    return _ORACLE_CACHE[name]
+
+
 def log(msg: str):
     print(msg, flush=True)
     sys.stdout.flush()

@@ -165,13 +165,23 @@ def test_deterministic():
 
 
 def test_order_preserving_maps_give_identical_results():
-    """Squared vs Euclidean distances on an integer grid compare identically."""
+    """Strictly increasing maps that are exact in float32 leave U and C bit-identical:
+    squared vs Euclidean distances on an integer grid, D -> 2D, and D -> rank(D)."""
     P = np.random.default_rng(21).integers(0, 8, size=(400, 3))
     Dsq = synth.pairwise_distances(P, squared=True)
     Deu = synth.pairwise_distances(P, squared=False)
     U1, C1 = gpu_cohesion(Dsq)
     U2, C2 = gpu_cohesion(Deu)
     assert np.array_equal(U1, U2) and np.array_equal(C1, C2)
+    D = synth.mixture8d(n=350, seed=23)
+    vals, inv = np.unique(D, return_inverse=True)  # dense ranks, 0 for the zero diagonal
+    Drank = inv.reshape(D.shape).astype(np.float32)
+    assert vals[0] == 0 and len(vals) < 2**24
+    U0, C0 = gpu_cohesion(D)
+    for Dm, what in ((2.0 * D, "2D"), (Drank, "rank(D)")):
+        Um, Cm = gpu_cohesion(np.ascontiguousarray(Dm, dtype=np.float32))
+        assert np.array_equal(Um, U0), what
+        assert np.array_equal(Cm.view(np.int32), C0.view(np.int32)), what
 
 
 def test_permutation_equivariance():
@@ -225,10 +235,16 @@ def test_config_uniform2d_n256_full():
     log(f"  max rel err {err:.3e}")
 
 
-def test_config_mixture8d_n4096_sampled():
+def test_config_mixture8d_n4096_full():
+    """The six-cluster mixture at n = 4096 against the full oracle (all 4096 rows)."""
+    from gpu_helpers import oracle_full_cached
+
     D = synth.mixture8d()
-    rows = np.sort(np.random.default_rng(2).choice(4096, size=48, replace=False))
-    U, C, err = parity(D, "mixture8d n=4096 (48 oracle rows)", rows=rows)
+    log("[parity] mixture8d n=4096 (full oracle)")
+    U, C = gpu_cohesion(D)
+    Uo, Co = oracle_full_cached("mixture8d_4096", D)
+    assert_u_equal(U, Uo, "mixture8d n=4096")
+    err = assert_c_close(C, Co, what="mixture8d n=4096")
     check_invariants(U, C, "mixture8d")
     log(f"  max rel err {err:.3e}")
 

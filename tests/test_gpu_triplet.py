@@ -113,10 +113,15 @@ def test_unsupported_option_combinations():
     assert e.value.status == pald.ERR_UNSUPPORTED
 
 
-def test_config_mixture8d_n4096_sampled():
-    """The configuration the two variants are compared on: 48 oracle rows + invariants."""
+def test_config_mixture8d_n4096_full():
+    """The configuration the two variants are compared on, against the full oracle."""
+    from gpu_helpers import assert_c_close, assert_u_equal, gpu_cohesion, oracle_full_cached
+
     D = synth.mixture8d()
-    rows = np.sort(np.random.default_rng(22).choice(4096, size=48, replace=False))
-    U, C, err = parity(D, "mixture8d n=4096 (48 oracle rows)", rows=rows)
+    log("[triplet] mixture8d n=4096 (full oracle)")
+    U, C = gpu_cohesion(D, variant="triplet")
+    Uo, Co = oracle_full_cached("mixture8d_4096", D)
+    assert_u_equal(U, Uo, "triplet mixture8d n=4096")
+    err = assert_c_close(C, Co, what="triplet mixture8d n=4096")
     check_invariants(U, C, "triplet mixture8d")
     log(f"  max rel err {err:.3e}")

@@ -246,6 +246,48 @@ __device__ __forceinline__ void tri_tile(int32_t k, int32_t &bx, int32_t &by) {
     bx = k - (int32_t)((int64_t)r * (r + 1) / 2);
 }
 
+// Launch order of the upper-triangular tiles, chosen for L2 reuse.
+//
+// Consecutive workgroups are dealt round robin over the 8 XCDs, each with its
+// own L2.  xcd_order() makes every XCD take a contiguous run of the order
+// instead (workgroup w of N runs on XCD w % 8 and gets position
+// (w % 8) * (N / 8) + ... + w / 8, a bijection of [0, N)), and grouped_tile()
+// lists the tiles by G x G groups (by rows of groups, tiles inside a group by
+// rows), so the tiles an XCD runs at the same time share a few row panels of
+// D and W in its L2 instead of each streaming its own.
+constexpr int TILE_GROUP = 8;
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int32_t xcd_order(int32_t w, int32_t N) {
+    const int32_t q = N / NUM_XCD, r = N % NUM_XCD, c = w % NUM_XCD, i = w / NUM_XCD;
+    return c * q + min(c, r) + i;
+}
+
+// k -> (bx, bz), bx <= bz < nb: the k-th tile in the grouped order.
+__device__ __forceinline__ void grouped_tile(int32_t k, int32_t nb, int32_t &bx, int32_t &bz) {
+    constexpr int64_t G = TILE_GROUP;
+    const int64_t nsb = (nb + G - 1) / G;
+    // tiles in the group rows before row S (all full): G^2 S(S-1)/2 + S G(G+1)/2
+    auto P = [&](int64_t S) { return G * G * S * (S - 1) / 2 + S * G * (G + 1) / 2; };
+    const double qa = 0.5 * G * G, qb = 0.5 * G * (G + 1) - 0.5 * G * G;
+    int64_t S = k > 0 ? (int64_t)((-qb + sqrt(qb * qb + 4.0 * qa * (double)k)) / (2.0 * qa)) : 0;
+    S = max((int64_t)0, min(S, nsb - 1));
+    while (S > 0 && P(S) > k) --S;
+    while (S + 1 < nsb && P(S + 1) <= k) ++S;
+    const int64_t wz = min(G, (int64_t)nb - S * G);
+    const int64_t rem = k - P(S), off = S * G * wz;
+    if (rem < off) {  // a full G-wide group left of the diagonal
+        const int64_t sx = rem / (G * wz), loc = rem % (G * wz);
+        bx = (int32_t)(sx * G + loc % G);
+        bz = (int32_t)(S * G + loc / G);
+    } else {          // the diagonal group: its own upper triangle
+        int32_t lx, lz;
+        tri_tile((int32_t)(rem - off), lx, lz);
+        bx = (int32_t)(S * G + lx);
+        bz = (int32_t)(S * G + lz);
+    }
+}
+
 // Loads 4 consecutive floats of row `row` starting at column `col` of a
 // row-major matrix as keys; out-of-range rows/columns give `fill`.
 __device__ __forceinline__ uint4 load_keys4(const float *__restrict__ M, int64_t ld, int64_t row,
@@ -292,8 +334,10 @@ __device__ __forceinline__ float weight_of(int32_t u) { return (float)(1.0 / (do
 // ---------------------------------------------------------------------------
 // Pass 1: focus sizes.
 //
-// Grid: tile0 + blockIdx.x enumerates the upper-triangular tiles (bx <= by) of
-// T x T tiles (large grids are launched in pieces); blockIdx.y is the z-chunk.  With one z-chunk the tile writes U (and,
+// Grid: blockIdx.x picks an upper-triangular T x T tile (bx <= by) in the
+// grouped, XCD-contiguous order of grouped_tile() / xcd_order(), offset by
+// tile0 (large grids are launched in pieces); blockIdx.y is the z-chunk.
+// With one z-chunk the tile writes U (and,
 // if W != nullptr, the weights W) directly; with several it atomically adds
 // its counts into U, which must be zero on entry.
 
@@ -421,7 +465,7 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT), PALD_P1_MIN_WAVES) v
     using Cfg = Pass1Cfg<T, RX, RY, KZ>;
     __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, by;
-    tri_tile(tile0 + (int32_t)blockIdx.x, bx, by);
+    grouped_tile(tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x), (int32_t)((n + T - 1) / T), bx, by);
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
     pass1_tile<T, RX, RY, KZ>((int)threadIdx.x, sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
@@ -458,8 +502,10 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // test between them.
 //
 // Each thread owns RX x 4 pairs (x, z).
-// Grid: tile0 + blockIdx.x enumerates the upper-triangular T x T tiles
-// (bx <= bz; large grids are launched in pieces); blockIdx.y is the y-chunk.  A tile with bx < bz writes C[X][Z] and C[Z][X];
+// Grid: blockIdx.x picks an upper-triangular T x T tile (bx <= bz) in the
+// grouped, XCD-contiguous order of grouped_tile() / xcd_order(), offset by
+// tile0 (large grids are launched in pieces); blockIdx.y is the y-chunk.  A
+// tile with bx < bz writes C[X][Z] and C[Z][X];
 // a diagonal tile covers every ordered pair of its block once as (x, z) and
 // writes only C[x][z].  With one y-chunk the tile writes
 // C = fl32(sum / (n-1)); otherwise it writes float64 partial sums
@@ -704,7 +750,7 @@ __global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT), PALD_P2_MIN_WAVES) void 
     using Cfg = Pass2Cfg<T, RX, KY>;
     __shared__ uint4 sm[Cfg::LDS_VEC];
     int32_t bx, bz;
-    tri_tile(tile0 + (int32_t)blockIdx.x, bx, bz);
+    grouped_tile(tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x), (int32_t)((n + T - 1) / T), bx, bz);
     const int64_t ybeg = (int64_t)blockIdx.y * y_per_chunk;
     const int64_t yend = min(n, ybeg + (int64_t)y_per_chunk);
     Pass2Out out{nullptr, 0, nullptr, nullptr};

@@ -155,3 +155,38 @@ def test_graph_distances_argument_errors():
     assert lib.pald_graph_distances(f, f, 4, 8, f, 8, f, ws - 8, None, 0) == pald.ERR_ARG
     assert lib.pald_graph_distances(f, f, 4, 8, f, 8, ctypes.c_void_p(0x10004), ws, None, 0) == pald.ERR_ARG
     assert lib.pald_graph_distances(f, f, 4, 8, f, 8, f, ws, None, 2) == pald.ERR_UNSUPPORTED
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/pald.h compiles as C99 with warnings as errors, and a C program
+    links against libpald.so and calls the host-only entry points."""
+    import subprocess
+
+    src = tmp_path / "use_pald.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <string.h>
+#include "pald.h"
+int main(void) {
+    pald_options opt;
+    memset(&opt, 0, sizeof opt);
+    opt.variant = PALD_VARIANT_PAIRWISE;
+    opt.accum = PALD_ACC_COMPENSATED;
+    if (pald_version() < 100) return 1;
+    if (strcmp(pald_status_string(PALD_ERR_ARG), "invalid argument") != 0) return 2;
+    if (pald_workspace_bytes(1000, &opt) < 1000u * 1000u * 4u) return 3;
+    if (pald_focus_sizes(NULL, 8, 8, NULL, 8, NULL, &opt) != PALD_ERR_ARG) return 4;
+    int64_t n[3] = {40, 300, 2};
+    int32_t items[4 * 64];
+    int32_t tiles1[3];
+    if (pald_batch_queue(3, n, NULL, 4, items, 64, tiles1) <= 0) return 5;
+    printf("ok\n");
+    return 0;
+}
+""")
+    exe = tmp_path / "use_pald"
+    lib_dir = os.path.dirname(pald.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           str(src), "-o", str(exe), "-L", lib_dir, "-lpald", f"-Wl,-rpath,{lib_dir}"])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0 and out.stdout.strip() == "ok", (out.returncode, out.stdout, out.stderr)

@@ -177,22 +177,25 @@ __global__ __launch_bounds__(BFS_THREADS) void graph_bfs_kernel(const int64_t *_
             const uint64_t vis = visit[v];
             uint64_t acc = 0;
             if (vis != all) {
+                // the sources that have not reached v yet; once all of them are
+                // found among the neighbours, the rest of the list adds nothing
+                const uint64_t missing = all & ~vis;
                 const int64_t e0 = min(max(row_ptr[v], (int64_t)0), nnz);
                 const int64_t e1 = min(max(row_ptr[v + 1], e0), nnz);
                 int64_t e = e0;
-                for (; e + 4 <= e1; e += 4) {  // four independent loads in flight
-                    uint32_t u[4];
+                for (; e + 8 <= e1 && (acc & missing) != missing; e += 8) {  // eight loads in flight
+                    uint32_t u[8];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) u[k] = (uint32_t)col[e + k];
+                    for (int k = 0; k < 8; ++k) u[k] = (uint32_t)col[e + k];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
+                    for (int k = 0; k < 8; ++k)
                         if (u[k] < (uint64_t)n) acc |= cur[u[k]];
                 }
-                for (; e < e1; ++e) {
+                for (; e < e1 && (acc & missing) != missing; ++e) {
                     const uint32_t u = (uint32_t)col[e];
                     if (u < (uint64_t)n) acc |= cur[u];
                 }
-                acc &= ~vis;
+                acc &= missing;
             }
             nxt[v] = acc;
             if (acc) {

@@ -91,6 +91,92 @@ __device__ __forceinline__ void focus_count8(int32_t (&c)[8], uint32_t x, const 
           [a3] "v"(a[3]), [a4] "v"(a[4]), [a5] "v"(a[5]), [a6] "v"(a[6]), [a7] "v"(a[7]));
 }
 
+// Focus counting over the lanes for 4 x 8 pairs (x_i, y_j), p = 8 i + j, the
+// 64 lanes holding 64 different z:
+//     c[p] += #{lanes : min(x[i], y[j]) <= a[p]}
+// with a[p] and the counts c[p] the same in every lane (c[p] in scalar
+// registers).  Operands are float bit patterns compared as floats: for finite
+// values >= 0 (and +inf padding) that is the order of the values, -0 equal to
+// +0 (denormals are compared exactly: the kernels are built without denormal
+// flushing).
+//
+// The vector unit makes each pair's 64-lane mask (min, compare) and the
+// scalar unit counts it (popcount, add).  Vector and scalar instructions
+// strictly alternate, so that one wave's scalar work issues next to another
+// wave's vector work on the same SIMD, and the mask of pair p is counted
+// while the mask of pair p + 2 is made: the masks of the last two pairs stay
+// in k[] and are counted by the next call (k[] must be 0 before the first
+// call; focus_mask_flush() counts what is left after the last).  A scalar
+// read of a vector-written scalar register needs no wait states (the
+// hardware interlocks it).  Registers only, no memory access; every lane
+// must be active.
+#define PALD_FMC(M, X, Y, Q, KP, CP, T)                                                                         \
+    "v_min_f32 %[m" #M "], %[x" #X "], %[y" #Y "]\n\t"                                                      \
+    "s_bcnt1_i32_b64 %[q" #Q "], %[k" #KP "]\n\t"                                                           \
+    "v_cmp_le_f32_e64 %[k" #KP "], %[m" #M "], %[a" #T "]\n\t"                                              \
+    "s_add_u32 %[c" #CP "], %[c" #CP "], %[q" #Q "]\n\t"
+__device__ __forceinline__ void focus_mask_count32(int32_t (&c)[32], const uint32_t (&x)[4], const uint32_t (&y)[8],
+                                                   const uint32_t (&a)[32], uint64_t (&k)[2]) {
+    uint32_t m0, m1, m2, m3, q0, q1;
+    asm(
+        PALD_FMC(0, 0, 0, 0, 0, 30, 0)
+        PALD_FMC(1, 0, 1, 1, 1, 31, 1)
+        PALD_FMC(2, 0, 2, 0, 0, 0, 2)
+        PALD_FMC(3, 0, 3, 1, 1, 1, 3)
+        PALD_FMC(0, 0, 4, 0, 0, 2, 4)
+        PALD_FMC(1, 0, 5, 1, 1, 3, 5)
+        PALD_FMC(2, 0, 6, 0, 0, 4, 6)
+        PALD_FMC(3, 0, 7, 1, 1, 5, 7)
+        PALD_FMC(0, 1, 0, 0, 0, 6, 8)
+        PALD_FMC(1, 1, 1, 1, 1, 7, 9)
+        PALD_FMC(2, 1, 2, 0, 0, 8, 10)
+        PALD_FMC(3, 1, 3, 1, 1, 9, 11)
+        PALD_FMC(0, 1, 4, 0, 0, 10, 12)
+        PALD_FMC(1, 1, 5, 1, 1, 11, 13)
+        PALD_FMC(2, 1, 6, 0, 0, 12, 14)
+        PALD_FMC(3, 1, 7, 1, 1, 13, 15)
+        PALD_FMC(0, 2, 0, 0, 0, 14, 16)
+        PALD_FMC(1, 2, 1, 1, 1, 15, 17)
+        PALD_FMC(2, 2, 2, 0, 0, 16, 18)
+        PALD_FMC(3, 2, 3, 1, 1, 17, 19)
+        PALD_FMC(0, 2, 4, 0, 0, 18, 20)
+        PALD_FMC(1, 2, 5, 1, 1, 19, 21)
+        PALD_FMC(2, 2, 6, 0, 0, 20, 22)
+        PALD_FMC(3, 2, 7, 1, 1, 21, 23)
+        PALD_FMC(0, 3, 0, 0, 0, 22, 24)
+        PALD_FMC(1, 3, 1, 1, 1, 23, 25)
+        PALD_FMC(2, 3, 2, 0, 0, 24, 26)
+        PALD_FMC(3, 3, 3, 1, 1, 25, 27)
+        PALD_FMC(0, 3, 4, 0, 0, 26, 28)
+        PALD_FMC(1, 3, 5, 1, 1, 27, 29)
+        PALD_FMC(2, 3, 6, 0, 0, 28, 30)
+        PALD_FMC(3, 3, 7, 1, 1, 29, 31)
+        : [c0] "+s"(c[0]), [c1] "+s"(c[1]), [c2] "+s"(c[2]), [c3] "+s"(c[3]), [c4] "+s"(c[4]), [c5] "+s"(c[5]),
+          [c6] "+s"(c[6]), [c7] "+s"(c[7]), [c8] "+s"(c[8]), [c9] "+s"(c[9]), [c10] "+s"(c[10]),
+          [c11] "+s"(c[11]), [c12] "+s"(c[12]), [c13] "+s"(c[13]), [c14] "+s"(c[14]), [c15] "+s"(c[15]),
+          [c16] "+s"(c[16]), [c17] "+s"(c[17]), [c18] "+s"(c[18]), [c19] "+s"(c[19]), [c20] "+s"(c[20]),
+          [c21] "+s"(c[21]), [c22] "+s"(c[22]), [c23] "+s"(c[23]), [c24] "+s"(c[24]), [c25] "+s"(c[25]),
+          [c26] "+s"(c[26]), [c27] "+s"(c[27]), [c28] "+s"(c[28]), [c29] "+s"(c[29]), [c30] "+s"(c[30]),
+          [c31] "+s"(c[31]), [k0] "+s"(k[0]), [k1] "+s"(k[1]), [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2),
+          [m3] "=&v"(m3), [q0] "=&s"(q0), [q1] "=&s"(q1)
+        : [x0] "v"(x[0]), [x1] "v"(x[1]), [x2] "v"(x[2]), [x3] "v"(x[3]), [y0] "v"(y[0]), [y1] "v"(y[1]),
+          [y2] "v"(y[2]), [y3] "v"(y[3]), [y4] "v"(y[4]), [y5] "v"(y[5]), [y6] "v"(y[6]), [y7] "v"(y[7]),
+          [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]), [a3] "v"(a[3]), [a4] "v"(a[4]), [a5] "v"(a[5]),
+          [a6] "v"(a[6]), [a7] "v"(a[7]), [a8] "v"(a[8]), [a9] "v"(a[9]), [a10] "v"(a[10]), [a11] "v"(a[11]),
+          [a12] "v"(a[12]), [a13] "v"(a[13]), [a14] "v"(a[14]), [a15] "v"(a[15]), [a16] "v"(a[16]),
+          [a17] "v"(a[17]), [a18] "v"(a[18]), [a19] "v"(a[19]), [a20] "v"(a[20]), [a21] "v"(a[21]),
+          [a22] "v"(a[22]), [a23] "v"(a[23]), [a24] "v"(a[24]), [a25] "v"(a[25]), [a26] "v"(a[26]),
+          [a27] "v"(a[27]), [a28] "v"(a[28]), [a29] "v"(a[29]), [a30] "v"(a[30]), [a31] "v"(a[31])
+        : "scc");
+}
+#undef PALD_FMC
+
+// The two masks focus_mask_count32 leaves in k[] (pairs 30 and 31).
+__device__ __forceinline__ void focus_mask_flush(int32_t (&c)[32], const uint64_t (&k)[2]) {
+    c[30] += __builtin_popcountll(k[0]);
+    c[31] += __builtin_popcountll(k[1]);
+}
+
 // Cohesion terms of one x and four z for one second point y, both directions:
 //   in_j  = [t_j <= min(a, b_j)]
 //   rf_j += in_j ? (t_j < b_j ? wx : whx) : 0          (c_xz, focus of x and y)
@@ -308,6 +394,21 @@ __device__ __forceinline__ uint4 load_keys4(const float *__restrict__ M, int64_t
     return r;
 }
 
+// 4 consecutive floats of row `row` from column `col` as raw bit patterns;
+// out-of-range rows/columns give `fill`.
+__device__ __forceinline__ uint4 load_raw4(const float *__restrict__ M, int64_t ld, int64_t row, int64_t col,
+                                           int64_t nrows, int64_t ncols, bool vec_ok, uint32_t fill) {
+    uint4 r = make_uint4(fill, fill, fill, fill);
+    if (row >= nrows) return r;
+    const float *p = M + row * ld + col;
+    if (vec_ok && col + 3 < ncols) return *reinterpret_cast<const uint4 *>(p);
+    if (col + 0 < ncols) r.x = __float_as_uint(p[0]);
+    if (col + 1 < ncols) r.y = __float_as_uint(p[1]);
+    if (col + 2 < ncols) r.z = __float_as_uint(p[2]);
+    if (col + 3 < ncols) r.w = __float_as_uint(p[3]);
+    return r;
+}
+
 // Same for plain float values (the weights W); out of range gives 0.
 __device__ __forceinline__ uint4 load_vals4(const float *__restrict__ M, int64_t ld, int64_t row,
                                             int64_t col, int64_t nrows, int64_t ncols, bool vec_ok) {
@@ -469,6 +570,210 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT), PALD_P1_MIN_WAVES) v
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
     pass1_tile<T, RX, RY, KZ>((int)threadIdx.x, sm, D, n, ldd, U, ldu, W, ldw, bx, by, zbeg, zend, atomic_mode != 0, vec_ok != 0);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1 with the lanes of a wave running over z.
+//
+// The kernel above gives every lane its own (x, y) pairs and streams z, which
+// costs three vector instructions per (x, y, z): min, compare, add-with-carry.
+// Here a wave owns 4 x 8 pairs whose keys d_xy are the same in every lane,
+// and its 64 lanes hold 64 different z.  One min and one compare per pair
+// give the 64-lane membership mask of a whole z block, and the scalar unit
+// counts it (popcount + add into a per-pair scalar register).  That leaves two
+// vector instructions per 64 (x, y, z) and moves the counting to the scalar
+// unit, which issues alongside the vector unit from the other waves of the
+// SIMD.
+//
+// Workgroup tile: TX = 16 x by TY = 16 y (4 x 2 waves of 4 x 8 pairs, 512
+// threads, 64 KB of LDS: two workgroups per CU, whose barriers are
+// independent; PALD_P1Z_GY = 4 gives 16 x 32 tiles of 1024 threads, one per
+// CU, about 3 % slower).  The tiles cover every pair x <= y exactly once:
+// tile (bi, bj) spans x in [TX bi, TX bi + TX), y in [TY bj, TY bj + TY), and
+// the tiles with floor(bi / S) <= bj, S = TY / TX, are enumerated as the S
+// parts of the square TY x TY tiles bx <= bj in the grouped order of
+// grouped_tile().  A tile counts all of its pairs but writes only those with
+// x <= y, and their mirror images.  Each stage stages 256 z of the TX + TY
+// rows of D the tile reads (d_zx = D[x][z] by symmetry) through LDS; lane l
+// works on z = 4 l + c, c = 0..3, of each of its wave's 12 rows (one block of
+// 32 pairs per c).
+constexpr int P1Z_WX = 4, P1Z_WY = 8;           // pairs per wave: 4 x by 8 y
+#ifndef PALD_P1Z_GY
+#define PALD_P1Z_GY 2
+#endif
+constexpr int P1Z_GX = 4, P1Z_GY = PALD_P1Z_GY; // waves per workgroup along x, y
+constexpr int P1Z_TX = P1Z_WX * P1Z_GX;         // x per tile (16)
+constexpr int P1Z_TY = P1Z_WY * P1Z_GY;         // y per tile (16)
+constexpr int P1Z_NT = 64 * P1Z_GX * P1Z_GY;    // threads (512)
+constexpr int P1Z_ZS = 256;                     // z per stage (4 per lane)
+constexpr int P1Z_ROWS = P1Z_TX + P1Z_TY;       // staged rows (32)
+constexpr int P1Z_STAGE_VEC = P1Z_ROWS * P1Z_ZS / 4;        // uint4 per stage
+constexpr int P1Z_VEC_PER_THREAD = P1Z_STAGE_VEC / P1Z_NT;  // 4
+constexpr int P1Z_SPLIT = P1Z_TY / P1Z_TX;                  // tiles per TY x TY square
+static_assert(P1Z_SPLIT * P1Z_TX == P1Z_TY, "the y side must be a multiple of the x side");
+static_assert(P1Z_STAGE_VEC % P1Z_NT == 0, "stage must split evenly over threads");
+static_assert(P1Z_WX == 4 && P1Z_WY == 8, "focus_mask_count32 counts 4 x 8 pairs");
+
+// Stage fetch of pass1z_focus_kernel for a stage that reaches past zend (or
+// an unaligned D): bounds-checked loads, +inf outside.  Kept out of line so
+// that the full-stage loads stay plain 16-byte loads.
+struct P1zStage {
+    uint4 v[P1Z_VEC_PER_THREAD];
+};
+
+__device__ __noinline__ P1zStage p1z_fetch_edge(const float *__restrict__ D, int64_t ldd, int64_t n, int64_t X0,
+                                                int64_t Y0, int wave, int lane, int64_t zs, int64_t zend,
+                                                bool vec_ok) {
+    P1zStage out;
+#pragma unroll
+    for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
+        const int r = wave + q * (P1Z_NT / 64);
+        const int64_t row = r < P1Z_TX ? X0 + r : Y0 + (r - P1Z_TX);
+        out.v[q] = load_raw4(D, ldd, row, zs + 4 * lane, n, zend, vec_ok, KEY_INF);
+    }
+    return out;
+}
+
+__global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__restrict__ D, int64_t n,
+                                                                 int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
+                                                                 float *__restrict__ W, int64_t ldw,
+                                                                 int32_t z_per_chunk, int32_t atomic_mode,
+                                                                 int32_t vec_ok, int32_t tile0) {
+    __shared__ uint4 sm[2 * P1Z_STAGE_VEC];
+    const int32_t k = tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    int32_t bx, bj;
+    grouped_tile(k / P1Z_SPLIT, (int32_t)((n + P1Z_TY - 1) / P1Z_TY), bx, bj);
+    const int64_t X0 = (int64_t)(P1Z_SPLIT * bx + k % P1Z_SPLIT) * P1Z_TX, Y0 = (int64_t)bj * P1Z_TY;
+    if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
+
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wx = wave % P1Z_GX, wy = wave / P1Z_GX;
+    const int64_t xw = X0 + wx * P1Z_WX, yw = Y0 + wy * P1Z_WY;
+
+    // d_xy of every pair (the same in every lane), kept in vector registers so
+    // that the scalar file holds only the counts; values stay float bit
+    // patterns (focus_mask_count32 compares them as floats)
+    // pair p = 8 i + j is (x, y) = (xw + i, yw + j)
+    uint32_t t[P1Z_WX * P1Z_WY];
+    int32_t cnt[P1Z_WX * P1Z_WY];
+    uint64_t carry[2] = {0, 0};
+#pragma unroll
+    for (int i = 0; i < P1Z_WX; ++i)
+#pragma unroll
+        for (int j = 0; j < P1Z_WY; ++j) {
+            const int64_t x = xw + i, y = yw + j;
+            uint32_t v = (x < n && y < n) ? __float_as_uint(D[x * ldd + y]) : 0u;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(t[i * P1Z_WY + j]) : "s"(v));
+            cnt[i * P1Z_WY + j] = 0;
+        }
+
+    const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
+    const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
+    const int32_t nst = (int32_t)((zend - zbeg + P1Z_ZS - 1) / P1Z_ZS);
+
+    // stage element v = tid + q NT: row r = v / 64 of the tile (x rows first,
+    // then y rows; r = wave + q NT / 64 is the same in the whole wave),
+    // z = zs + 4 (v % 64) = zs + 4 lane.  Raw float bits, +inf past zend.
+    // Stages that lie inside [zbeg, zend) of a tile whose rows all exist
+    // (every tile but those at the edge of D) load with plain 16-byte loads
+    // from fixed row pointers and one 32-bit offset; the others go through the
+    // bounds-checked p1z_fetch_edge().
+    const bool rows_in = vec_ok && X0 + P1Z_TX <= n && Y0 + P1Z_TY <= n;
+    const int32_t nst_fast = rows_in ? (int32_t)((zend - zbeg) / P1Z_ZS) : 0;  // leading stages needing no checks
+    const char *rowp[P1Z_VEC_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
+        const int r = wave + q * (P1Z_NT / 64);
+        const int64_t row = r < P1Z_TX ? X0 + r : Y0 + (r - P1Z_TX);
+        rowp[q] = reinterpret_cast<const char *>(D + min(row, n - 1) * ldd + zbeg);
+    }
+    uint4 pre[P1Z_VEC_PER_THREAD];
+    auto fetch = [&](int32_t st) {  // stage st: z = zbeg + 256 st + ...
+        if (st < nst_fast) {
+            // byte offset in the row: below 4 n < 2^32
+            const uint32_t off = ((uint32_t)st * P1Z_ZS + 4u * (uint32_t)lane) * (uint32_t)sizeof(float);
+#pragma unroll
+            for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
+                const float4 v = *reinterpret_cast<const float4 *>(rowp[q] + off);
+                pre[q] = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                                    __float_as_uint(v.w));
+            }
+        } else {
+            const P1zStage e =
+                p1z_fetch_edge(D, ldd, n, X0, Y0, wave, lane, zbeg + (int64_t)st * P1Z_ZS, zend, vec_ok);
+#pragma unroll
+            for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) pre[q] = e.v[q];
+        }
+    };
+    // LDS layout of a stage: [row][c][lane], element = z zs + 4 lane + c, so
+    // that the reads of one component c are contiguous over the lanes
+    uint32_t *smw = reinterpret_cast<uint32_t *>(sm);
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
+            uint32_t *dst = smw + buf * (4 * P1Z_STAGE_VEC) + (wave + q * (P1Z_NT / 64)) * P1Z_ZS + lane;
+            dst[0] = pre[q].x;
+            dst[64] = pre[q].y;
+            dst[128] = pre[q].z;
+            dst[192] = pre[q].w;
+        }
+    };
+
+    if (nst > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int32_t st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) fetch(st + 1);
+        // component c + 1 is read before the block of component c runs (the
+        // scheduling barriers keep the reads there), so that they overlap it
+        const uint32_t *sb = smw + buf * (4 * P1Z_STAGE_VEC) + lane;
+        uint32_t av[2][P1Z_WX], bv[2][P1Z_WY];
+        auto read_comp = [&](int c) {
+#pragma unroll
+            for (int i = 0; i < P1Z_WX; ++i) av[c & 1][i] = sb[(wx * P1Z_WX + i) * P1Z_ZS + 64 * c];
+#pragma unroll
+            for (int j = 0; j < P1Z_WY; ++j) bv[c & 1][j] = sb[(P1Z_TX + wy * P1Z_WY + j) * P1Z_ZS + 64 * c];
+        };
+        read_comp(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c + 1 < 4) read_comp(c + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (st + 1 < nst) stash(buf ^ 1);
+        __syncthreads();
+    }
+
+    focus_mask_flush(cnt, carry);
+    // epilogue: lane p (p < 32) takes pair p
+    int32_t mine = 0;
+#pragma unroll
+    for (int p = 0; p < P1Z_WX * P1Z_WY; ++p) mine = lane == p ? cnt[p] : mine;
+    if (lane >= P1Z_WX * P1Z_WY) return;
+    const int64_t x = xw + lane / P1Z_WY, y = yw + lane % P1Z_WY;
+    if (x >= n || y >= n || x > y) return;
+    const bool mirror = x != y;
+    if (atomic_mode) {
+        atomicAdd(&U[x * ldu + y], mine);
+        if (mirror) atomicAdd(&U[y * ldu + x], mine);
+        return;
+    }
+    if (U) {
+        U[x * ldu + y] = mine;
+        if (mirror) U[y * ldu + x] = mine;
+    }
+    if (W) {
+        const float w = mirror ? weight_of(mine) : 0.0f;
+        W[x * ldw + y] = w;
+        if (mirror) W[y * ldw + x] = w;
+    }
 }
 
 // W_xy = fl32(1/U_xy) off the diagonal, 0 on it (used after a split pass 1).

@@ -30,6 +30,14 @@ using namespace pald_host;
 #endif
 constexpr int P1_T = 128, P1_RX = PALD_P1_RX, P1_RY = 8, P1_KZ = 16;
 using P1 = Pass1Cfg<P1_T, P1_RX, P1_RY, P1_KZ>;
+// PALD_P1_LANES_Z = 1 (default): pass 1 runs pass1z_focus_kernel (lanes over z,
+// counts on the scalar unit); 0: pass1_focus_kernel (lanes over pairs)
+#ifndef PALD_P1_LANES_Z
+#define PALD_P1_LANES_Z 1
+#endif
+constexpr bool P1_LANES_Z = PALD_P1_LANES_Z != 0;
+// z granularity of a pass-1 chunk: one stage of whichever kernel runs
+constexpr int P1_ZQ = P1_LANES_Z ? P1Z_ZS : P1_KZ;
 // pass 2: symmetric 64 x 64 (x,z) tiles, P2_RX x 4 pairs (both directions) per thread,
 // 16 y rows per stage
 #ifndef PALD_P2_RX
@@ -45,6 +53,7 @@ constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
 // Large tile grids are launched in pieces so that no single dispatch runs for
 // more than a few seconds (n = 65536: about 2-3 s per piece).
 constexpr int64_t P1_TILES_PER_LAUNCH = 32768;
+constexpr int64_t P1Z_TILES_PER_LAUNCH = 1 << 20;  // n = 65536: 8 launches of about 1 s
 constexpr int64_t P2_TILES_PER_LAUNCH = 65536;
 constexpr int64_t TRI_TILES_PER_LAUNCH = 8192;
 
@@ -89,16 +98,21 @@ struct Plan {
 pald_status make_plan(int64_t n, const Opts &o, Plan &p) {
     p = Plan{};
     p.n = n;
-    p.nb1 = ceil_div(n, P1_T);
-    p.tiles1 = p.nb1 * (p.nb1 + 1) / 2;
+    if (P1_LANES_Z) {  // P1Z_SPLIT tiles per upper-triangular P1Z_TY x P1Z_TY square
+        p.nb1 = ceil_div(n, P1Z_TY);
+        p.tiles1 = P1Z_SPLIT * (p.nb1 * (p.nb1 + 1) / 2);
+    } else {
+        p.nb1 = ceil_div(n, P1_T);
+        p.tiles1 = p.nb1 * (p.nb1 + 1) / 2;
+    }
     if (p.tiles1 > INT32_MAX) return PALD_ERR_UNSUPPORTED;
     int64_t zc = o.z_chunks;
     if (zc == 0) {
         zc = ceil_div(TARGET_WORKGROUPS, p.tiles1);
-        zc = std::min<int64_t>(zc, std::max<int64_t>(1, n / (4 * P1_KZ)));
+        zc = std::min<int64_t>(zc, std::max<int64_t>(1, n / (4 * P1_ZQ)));
     }
-    zc = std::max<int64_t>(1, std::min<int64_t>(zc, ceil_div(n, P1_KZ)));
-    p.z_per_chunk = (int32_t)(ceil_div(ceil_div(n, zc), P1_KZ) * P1_KZ);
+    zc = std::max<int64_t>(1, std::min<int64_t>(zc, ceil_div(n, P1_ZQ)));
+    p.z_per_chunk = (int32_t)(ceil_div(ceil_div(n, zc), P1_ZQ) * P1_ZQ);
     p.z_chunks = (int32_t)ceil_div(n, p.z_per_chunk);
 
     p.nb2 = ceil_div(n, P2_T);
@@ -133,11 +147,16 @@ pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_
                       int64_t ldw, const Plan &p, hipStream_t s, bool timing) {
     const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     if (p.z_chunks == 1) {
-        for (int64_t t0 = 0; t0 < p.tiles1; t0 += P1_TILES_PER_LAUNCH) {
+        const int64_t per_launch = P1_LANES_Z ? P1Z_TILES_PER_LAUNCH : P1_TILES_PER_LAUNCH;
+        for (int64_t t0 = 0; t0 < p.tiles1; t0 += per_launch) {
             ScopedTiming tm(timing, 0, s);
-            const unsigned g = (unsigned)std::min<int64_t>(P1_TILES_PER_LAUNCH, p.tiles1 - t0);
-            pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ>
-                <<<dim3(g, 1), P1::NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec, (int32_t)t0);
+            const unsigned g = (unsigned)std::min<int64_t>(per_launch, p.tiles1 - t0);
+            if (P1_LANES_Z)
+                pass1z_focus_kernel<<<dim3(g, 1), P1Z_NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec,
+                                                                  (int32_t)t0);
+            else
+                pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ>
+                    <<<dim3(g, 1), P1::NT, 0, s>>>(D, n, ldd, U, ldu, W, ldw, p.z_per_chunk, 0, vec, (int32_t)t0);
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
         return PALD_OK;
@@ -149,8 +168,12 @@ pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_
     }
     {
         ScopedTiming tm(timing, 0, s);
-        pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1::NT, 0, s>>>(
-            D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
+        if (P1_LANES_Z)
+            pass1z_focus_kernel<<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1Z_NT, 0, s>>>(
+                D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
+        else
+            pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1::NT, 0,
+                                                            s>>>(D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     if (W) {

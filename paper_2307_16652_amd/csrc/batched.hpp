@@ -83,8 +83,22 @@ constexpr int BATCH_P2S_T = 32, BATCH_P2S_RX = BATCH_THREADS == 256 ? 1 : 0;
 using BatchP2S = Pass2Cfg<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY>;
 static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS && BatchP2S::NT == BATCH_THREADS,
               "all batched tile shapes use one workgroup size");
+// Pass-1 items (64 x 64 pair regions) run as 8 x 16 lanes-over-z tiles
+// (2 x 2 waves of 4 x 8 pairs, 2 z per lane and 128 z per stage: short
+// matrices waste less of their last stage) when PALD_BATCH_P1_LANES_Z = 1
+// (default), else as one lanes-over-pairs pass1_tile.
+#ifndef PALD_BATCH_P1_LANES_Z
+#define PALD_BATCH_P1_LANES_Z 0
+#endif
+#ifndef PALD_BATCH_P1Z_NC
+#define PALD_BATCH_P1Z_NC 2
+#endif
+using BatchP1z = P1zCfg<2, 2, PALD_BATCH_P1Z_NC>;
+static_assert(BatchP1z::NT == BATCH_THREADS || !PALD_BATCH_P1_LANES_Z, "lanes-over-z pass-1 tiles use 4 waves");
+static_assert(BATCH_P1_T % BatchP1z::TX == 0 && BATCH_P1_T % BatchP1z::TY == 0, "sub-tiles must tile a pass-1 item");
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int BATCH_LDS_VEC = cmax(BatchP1::LDS_VEC, cmax(BatchP2::LDS_VEC, BatchP2S::LDS_VEC));
+constexpr int BATCH_LDS_VEC =
+    cmax(PALD_BATCH_P1_LANES_Z ? BatchP1z::LDS_WORDS / 4 : BatchP1::LDS_VEC, cmax(BatchP2::LDS_VEC, BatchP2S::LDS_VEC));
 
 // Counter layout (uint32): [0] queue head, [1 .. count] pass-1 done counts,
 // [1 + count ..] per-tile arrival counters of split pass-2 tiles.
@@ -142,8 +156,21 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                 int32_t bx, by;
                 tri_tile(tile, bx, by);
                 int32_t *Um = U ? U + moff : nullptr;
-                pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(opaque_tid(), sm, D + moff, n, n, Um, n, Wr + mwoff, mldw, bx, by, 0, n,
-                                                 false, vec_d);
+                if (PALD_BATCH_P1_LANES_Z) {
+                    // the region's sub-tiles holding a pair x <= y (each pair once:
+                    // a sub-tile writes its pairs x <= y and their mirrors)
+                    for (int sy = 0; sy < BATCH_P1_T / BatchP1z::TY; ++sy)
+                        for (int sx = 0; sx < BATCH_P1_T / BatchP1z::TX; ++sx) {
+                            const int64_t X0 = (int64_t)bx * BATCH_P1_T + sx * BatchP1z::TX;
+                            const int64_t Y0 = (int64_t)by * BATCH_P1_T + sy * BatchP1z::TY;
+                            if (X0 >= n || Y0 >= n || X0 > Y0 + (BatchP1z::TY - 1)) continue;
+                            pass1z_tile<2, 2, PALD_BATCH_P1Z_NC>(opaque_tid(), reinterpret_cast<uint32_t *>(sm), D + moff, n, n, Um, n,
+                                                 Wr + mwoff, mldw, X0, Y0, 0, n, false, vec_d);
+                        }
+                } else {
+                    pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(opaque_tid(), sm, D + moff, n, n, Um, n, Wr + mwoff, mldw,
+                                                               bx, by, 0, n, false, vec_d);
+                }
                 __threadfence();  // release this thread's U / W stores at device scope
                 __syncthreads();
                 if (tid == 0) atomicAdd(&done1[mi], 1u);

@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace pald {
 
 constexpr uint32_t KEY_INF = 0x7f800000u;  // key of +infinity: larger than every finite key
@@ -585,179 +587,212 @@ __global__ __launch_bounds__((Pass1Cfg<T, RX, RY, KZ>::NT), PALD_P1_MIN_WAVES) v
 // unit, which issues alongside the vector unit from the other waves of the
 // SIMD.
 //
-// Workgroup tile: TX = 16 x by TY = 16 y (4 x 2 waves of 4 x 8 pairs, 512
-// threads, 64 KB of LDS: two workgroups per CU, whose barriers are
-// independent; PALD_P1Z_GY = 4 gives 16 x 32 tiles of 1024 threads, one per
-// CU, about 3 % slower).  The tiles cover every pair x <= y exactly once:
-// tile (bi, bj) spans x in [TX bi, TX bi + TX), y in [TY bj, TY bj + TY), and
-// the tiles with floor(bi / S) <= bj, S = TY / TX, are enumerated as the S
-// parts of the square TY x TY tiles bx <= bj in the grouped order of
-// grouped_tile().  A tile counts all of its pairs but writes only those with
-// x <= y, and their mirror images.  Each stage stages 256 z of the TX + TY
-// rows of D the tile reads (d_zx = D[x][z] by symmetry) through LDS; lane l
-// works on z = 4 l + c, c = 0..3, of each of its wave's 12 rows (one block of
-// 32 pairs per c).
-constexpr int P1Z_WX = 4, P1Z_WY = 8;           // pairs per wave: 4 x by 8 y
-#ifndef PALD_P1Z_GY
-#define PALD_P1Z_GY 2
-#endif
-constexpr int P1Z_GX = 4, P1Z_GY = PALD_P1Z_GY; // waves per workgroup along x, y
-constexpr int P1Z_TX = P1Z_WX * P1Z_GX;         // x per tile (16)
-constexpr int P1Z_TY = P1Z_WY * P1Z_GY;         // y per tile (16)
-constexpr int P1Z_NT = 64 * P1Z_GX * P1Z_GY;    // threads (512)
-constexpr int P1Z_ZS = 256;                     // z per stage (4 per lane)
-constexpr int P1Z_ROWS = P1Z_TX + P1Z_TY;       // staged rows (32)
-constexpr int P1Z_STAGE_VEC = P1Z_ROWS * P1Z_ZS / 4;        // uint4 per stage
-constexpr int P1Z_VEC_PER_THREAD = P1Z_STAGE_VEC / P1Z_NT;  // 4
-constexpr int P1Z_SPLIT = P1Z_TY / P1Z_TX;                  // tiles per TY x TY square
-static_assert(P1Z_SPLIT * P1Z_TX == P1Z_TY, "the y side must be a multiple of the x side");
-static_assert(P1Z_STAGE_VEC % P1Z_NT == 0, "stage must split evenly over threads");
-static_assert(P1Z_WX == 4 && P1Z_WY == 8, "focus_mask_count32 counts 4 x 8 pairs");
-
-// Stage fetch of pass1z_focus_kernel for a stage that reaches past zend (or
-// an unaligned D): bounds-checked loads, +inf outside.  Kept out of line so
-// that the full-stage loads stay plain 16-byte loads.
-struct P1zStage {
-    uint4 v[P1Z_VEC_PER_THREAD];
+// A tile counts all of its pairs but writes only those with x <= y, and
+// their mirror images.  Each stage stages ZS z of the TX + TY rows of D the
+// tile reads (d_zx = D[x][z] by symmetry) through LDS; lane l works on
+// z = NC l + c, c < NC, of each of its wave's 12 rows (one block of 32 pairs
+// per c).
+//
+// Configuration of a lanes-over-z pass-1 tile: GX x GY waves of 4 x 8 pairs
+// (TX = 4 GX x, TY = 8 GY y), NC z per lane and stage (ZS = 64 NC z staged
+// per stage for the TX + TY rows of the tile).
+template <int GX, int GY, int NC>
+struct P1zCfg {
+    static constexpr int WX = 4, WY = 8;
+    static constexpr int TX = WX * GX, TY = WY * GY;
+    static constexpr int NW = GX * GY;          // waves
+    static constexpr int NT = 64 * NW;          // threads
+    static constexpr int ZS = 64 * NC;          // z per stage
+    static constexpr int ROWS = TX + TY;        // staged rows
+    static constexpr int ROWS_PER_WAVE = ROWS / NW;  // rows each wave loads per stage
+    static constexpr int LDS_WORDS = 2 * ROWS * ZS;  // double-buffered stage (uint32)
+    static_assert(ROWS % NW == 0, "the staged rows must split evenly over the waves");
+    static_assert(NC == 2 || NC == 4, "2 or 4 z per lane");
 };
 
-__device__ __noinline__ P1zStage p1z_fetch_edge(const float *__restrict__ D, int64_t ldd, int64_t n, int64_t X0,
-                                                int64_t Y0, int wave, int lane, int64_t zs, int64_t zend,
-                                                bool vec_ok) {
-    P1zStage out;
+// NC consecutive floats per lane as raw bits (a uint2 or a uint4).
+template <int NC>
+struct P1zVec;
+template <>
+struct P1zVec<4> {
+    uint32_t v[4];
+};
+template <>
+struct P1zVec<2> {
+    uint32_t v[2];
+};
+
+// The staged values one thread loads for one stage.
+template <int RPW, int NC>
+struct P1zStage {
+    P1zVec<NC> r[RPW];
+};
+
+// Stage fetch for a stage that reaches past zend (or an unaligned D):
+// bounds-checked loads, +inf outside.  Kept out of line so that the
+// full-stage loads stay plain vector loads.  Row q of this wave is tile row
+// wave + q NW (x rows first, then y rows); lane l loads z = zs + NC l + c.
+template <int GX, int GY, int NC>
+__device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetch_edge(
+    const float *__restrict__ D, int64_t ldd, int64_t n, int64_t X0, int64_t Y0, int wave, int lane, int64_t zs,
+    int64_t zend, bool vec_ok) {
+    using Cfg = P1zCfg<GX, GY, NC>;
+    P1zStage<Cfg::ROWS_PER_WAVE, NC> out;
 #pragma unroll
-    for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
-        const int r = wave + q * (P1Z_NT / 64);
-        const int64_t row = r < P1Z_TX ? X0 + r : Y0 + (r - P1Z_TX);
-        out.v[q] = load_raw4(D, ldd, row, zs + 4 * lane, n, zend, vec_ok, KEY_INF);
+    for (int q = 0; q < Cfg::ROWS_PER_WAVE; ++q) {
+        const int r = wave + q * Cfg::NW;
+        const int64_t row = r < Cfg::TX ? X0 + r : Y0 + (r - Cfg::TX);
+        const int64_t z0 = zs + (int64_t)NC * lane;
+        if (NC == 4) {
+            const uint4 v = load_raw4(D, ldd, row, z0, n, zend, vec_ok, KEY_INF);
+            out.r[q].v[0] = v.x;
+            out.r[q].v[NC > 1 ? 1 : 0] = v.y;
+            out.r[q].v[NC > 2 ? 2 : 0] = v.z;
+            out.r[q].v[NC > 3 ? 3 : 0] = v.w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                out.r[q].v[c] = (row < n && z0 + c < zend) ? __float_as_uint(D[row * ldd + z0 + c]) : KEY_INF;
+        }
     }
     return out;
 }
 
-__global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__restrict__ D, int64_t n,
-                                                                 int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
-                                                                 float *__restrict__ W, int64_t ldw,
-                                                                 int32_t z_per_chunk, int32_t atomic_mode,
-                                                                 int32_t vec_ok, int32_t tile0) {
-    __shared__ uint4 sm[2 * P1Z_STAGE_VEC];
-    const int32_t k = tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x);
-    int32_t bx, bj;
-    grouped_tile(k / P1Z_SPLIT, (int32_t)((n + P1Z_TY - 1) / P1Z_TY), bx, bj);
-    const int64_t X0 = (int64_t)(P1Z_SPLIT * bx + k % P1Z_SPLIT) * P1Z_TX, Y0 = (int64_t)bj * P1Z_TY;
-    if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
-
-    const int tid = (int)threadIdx.x;
+// One lanes-over-z pass-1 tile: pairs x in [X0, X0 + TX), y in [Y0, Y0 + TY),
+// z over [zbeg, zend).  Called by every thread of a workgroup of Cfg::NT
+// threads (tid = thread index); `smw` points to Cfg::LDS_WORDS words of LDS.
+// Writes U (if non-null) and W (if non-null) for the tile's pairs with
+// x <= y and their mirror images, or, in atomic mode, adds the counts into U.
+// Ends with a workgroup barrier, so the LDS can be reused at once.
+template <int GX, int GY, int NC>
+__device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float *__restrict__ D, int64_t n,
+                                            int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
+                                            float *__restrict__ W, int64_t ldw, int64_t X0, int64_t Y0,
+                                            int64_t zbeg, int64_t zend, bool atomic_mode, bool vec_ok) {
+    using Cfg = P1zCfg<GX, GY, NC>;
+    constexpr int RPW = Cfg::ROWS_PER_WAVE;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wx = wave % P1Z_GX, wy = wave / P1Z_GX;
-    const int64_t xw = X0 + wx * P1Z_WX, yw = Y0 + wy * P1Z_WY;
+    const int wx = wave % GX, wy = wave / GX;
+    const int64_t xw = X0 + wx * Cfg::WX, yw = Y0 + wy * Cfg::WY;
 
     // d_xy of every pair (the same in every lane), kept in vector registers so
     // that the scalar file holds only the counts; values stay float bit
-    // patterns (focus_mask_count32 compares them as floats)
-    // pair p = 8 i + j is (x, y) = (xw + i, yw + j)
-    uint32_t t[P1Z_WX * P1Z_WY];
-    int32_t cnt[P1Z_WX * P1Z_WY];
+    // patterns (focus_mask_count32 compares them as floats).  Pair p = 8 i + j
+    // is (x, y) = (xw + i, yw + j).
+    uint32_t t[Cfg::WX * Cfg::WY];
+    int32_t cnt[Cfg::WX * Cfg::WY];
     uint64_t carry[2] = {0, 0};
 #pragma unroll
-    for (int i = 0; i < P1Z_WX; ++i)
+    for (int i = 0; i < Cfg::WX; ++i)
 #pragma unroll
-        for (int j = 0; j < P1Z_WY; ++j) {
+        for (int j = 0; j < Cfg::WY; ++j) {
             const int64_t x = xw + i, y = yw + j;
             uint32_t v = (x < n && y < n) ? __float_as_uint(D[x * ldd + y]) : 0u;
-            asm volatile("v_mov_b32 %0, %1" : "=v"(t[i * P1Z_WY + j]) : "s"(v));
-            cnt[i * P1Z_WY + j] = 0;
+            asm volatile("v_mov_b32 %0, %1" : "=v"(t[i * Cfg::WY + j]) : "s"(v));
+            cnt[i * Cfg::WY + j] = 0;
         }
 
-    const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
-    const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
-    const int32_t nst = (int32_t)((zend - zbeg + P1Z_ZS - 1) / P1Z_ZS);
-
-    // stage element v = tid + q NT: row r = v / 64 of the tile (x rows first,
-    // then y rows; r = wave + q NT / 64 is the same in the whole wave),
-    // z = zs + 4 (v % 64) = zs + 4 lane.  Raw float bits, +inf past zend.
-    // Stages that lie inside [zbeg, zend) of a tile whose rows all exist
-    // (every tile but those at the edge of D) load with plain 16-byte loads
-    // from fixed row pointers and one 32-bit offset; the others go through the
-    // bounds-checked p1z_fetch_edge().
-    const bool rows_in = vec_ok && X0 + P1Z_TX <= n && Y0 + P1Z_TY <= n;
-    const int32_t nst_fast = rows_in ? (int32_t)((zend - zbeg) / P1Z_ZS) : 0;  // leading stages needing no checks
-    const char *rowp[P1Z_VEC_PER_THREAD];
+    const int32_t nst = (int32_t)((zend - zbeg + Cfg::ZS - 1) / Cfg::ZS);
+    // Stages that lie inside [zbeg, zend) of a tile whose rows all exist load
+    // from fixed row pointers and one 32-bit offset, without checks (vector
+    // loads when the rows are 16-byte aligned, else one load per value); the
+    // others go through the bounds-checked p1z_fetch_edge().
+    const bool rows_in = X0 + Cfg::TX <= n && Y0 + Cfg::TY <= n;
+    const int32_t nst_fast = rows_in ? (int32_t)((zend - zbeg) / Cfg::ZS) : 0;  // leading stages needing no checks
+    const char *rowp[RPW];
 #pragma unroll
-    for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
-        const int r = wave + q * (P1Z_NT / 64);
-        const int64_t row = r < P1Z_TX ? X0 + r : Y0 + (r - P1Z_TX);
+    for (int q = 0; q < RPW; ++q) {
+        const int r = wave + q * Cfg::NW;
+        const int64_t row = r < Cfg::TX ? X0 + r : Y0 + (r - Cfg::TX);
         rowp[q] = reinterpret_cast<const char *>(D + min(row, n - 1) * ldd + zbeg);
     }
-    uint4 pre[P1Z_VEC_PER_THREAD];
-    auto fetch = [&](int32_t st) {  // stage st: z = zbeg + 256 st + ...
-        if (st < nst_fast) {
-            // byte offset in the row: below 4 n < 2^32
-            const uint32_t off = ((uint32_t)st * P1Z_ZS + 4u * (uint32_t)lane) * (uint32_t)sizeof(float);
+    // The stage loop, instantiated for aligned rows (VEC: vector loads) and for
+    // unaligned ones (one load per value); one tile runs one of the two.
+    auto run = [&](auto vec_tag) {
+        constexpr bool VEC = decltype(vec_tag)::value;
+        P1zStage<RPW, NC> pre;
+        auto fetch = [&](int32_t st) {  // stage st: z = zbeg + ZS st + ...
+            if (st < nst_fast) {
+                // byte offset in the row: below 4 n, and n x n floats fit in memory
+                const uint32_t off =
+                    ((uint32_t)st * Cfg::ZS + (uint32_t)NC * (uint32_t)lane) * (uint32_t)sizeof(float);
 #pragma unroll
-            for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
-                const float4 v = *reinterpret_cast<const float4 *>(rowp[q] + off);
-                pre[q] = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
-                                    __float_as_uint(v.w));
+                for (int q = 0; q < RPW; ++q) {
+                    if constexpr (!VEC) {
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            pre.r[q].v[c] = __float_as_uint(reinterpret_cast<const float *>(rowp[q] + off)[c]);
+                    } else if constexpr (NC == 4) {
+                        const float4 v = *reinterpret_cast<const float4 *>(rowp[q] + off);
+                        pre.r[q].v[0] = __float_as_uint(v.x);
+                        pre.r[q].v[1] = __float_as_uint(v.y);
+                        pre.r[q].v[2] = __float_as_uint(v.z);
+                        pre.r[q].v[3] = __float_as_uint(v.w);
+                    } else {
+                        const float2 v = *reinterpret_cast<const float2 *>(rowp[q] + off);
+                        pre.r[q].v[0] = __float_as_uint(v.x);
+                        pre.r[q].v[1] = __float_as_uint(v.y);
+                    }
+                }
+            } else {
+                pre = p1z_fetch_edge<GX, GY, NC>(D, ldd, n, X0, Y0, wave, lane, zbeg + (int64_t)st * Cfg::ZS, zend,
+                                                 VEC);
             }
-        } else {
-            const P1zStage e =
-                p1z_fetch_edge(D, ldd, n, X0, Y0, wave, lane, zbeg + (int64_t)st * P1Z_ZS, zend, vec_ok);
-#pragma unroll
-            for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) pre[q] = e.v[q];
-        }
-    };
-    // LDS layout of a stage: [row][c][lane], element = z zs + 4 lane + c, so
-    // that the reads of one component c are contiguous over the lanes
-    uint32_t *smw = reinterpret_cast<uint32_t *>(sm);
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < P1Z_VEC_PER_THREAD; ++q) {
-            uint32_t *dst = smw + buf * (4 * P1Z_STAGE_VEC) + (wave + q * (P1Z_NT / 64)) * P1Z_ZS + lane;
-            dst[0] = pre[q].x;
-            dst[64] = pre[q].y;
-            dst[128] = pre[q].z;
-            dst[192] = pre[q].w;
-        }
-    };
-
-    if (nst > 0) {
-        fetch(0);
-        stash(0);
-    }
-    __syncthreads();
-    for (int32_t st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) fetch(st + 1);
-        // component c + 1 is read before the block of component c runs (the
-        // scheduling barriers keep the reads there), so that they overlap it
-        const uint32_t *sb = smw + buf * (4 * P1Z_STAGE_VEC) + lane;
-        uint32_t av[2][P1Z_WX], bv[2][P1Z_WY];
-        auto read_comp = [&](int c) {
-#pragma unroll
-            for (int i = 0; i < P1Z_WX; ++i) av[c & 1][i] = sb[(wx * P1Z_WX + i) * P1Z_ZS + 64 * c];
-#pragma unroll
-            for (int j = 0; j < P1Z_WY; ++j) bv[c & 1][j] = sb[(P1Z_TX + wy * P1Z_WY + j) * P1Z_ZS + 64 * c];
         };
-        read_comp(0);
+        // LDS layout of a stage: [row][c][lane], element = z zs + NC lane + c,
+        // so that the reads of one component c are contiguous over the lanes
+        auto stash = [&](int buf) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c + 1 < 4) read_comp(c + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
-            __builtin_amdgcn_sched_barrier(0);
+            for (int q = 0; q < RPW; ++q) {
+                uint32_t *dst = smw + buf * (Cfg::ROWS * Cfg::ZS) + (wave + q * Cfg::NW) * Cfg::ZS + lane;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) dst[64 * c] = pre.r[q].v[c];
+            }
+        };
+
+        if (nst > 0) {
+            fetch(0);
+            stash(0);
         }
-        if (st + 1 < nst) stash(buf ^ 1);
         __syncthreads();
-    }
+        for (int32_t st = 0; st < nst; ++st) {
+            const int buf = st & 1;
+            if (st + 1 < nst) fetch(st + 1);
+            // component c + 1 is read before the block of component c runs (the
+            // scheduling barriers keep the reads there), so that they overlap it
+            const uint32_t *sb = smw + buf * (Cfg::ROWS * Cfg::ZS) + lane;
+            uint32_t av[2][Cfg::WX], bv[2][Cfg::WY];
+            auto read_comp = [&](int c) {
+#pragma unroll
+                for (int i = 0; i < Cfg::WX; ++i) av[c & 1][i] = sb[(wx * Cfg::WX + i) * Cfg::ZS + 64 * c];
+#pragma unroll
+                for (int j = 0; j < Cfg::WY; ++j) bv[c & 1][j] = sb[(Cfg::TX + wy * Cfg::WY + j) * Cfg::ZS + 64 * c];
+            };
+            read_comp(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (c + 1 < NC) read_comp(c + 1);
+                __builtin_amdgcn_sched_barrier(0);
+                focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (st + 1 < nst) stash(buf ^ 1);
+            __syncthreads();
+        }
+    };
+    if (vec_ok)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 
     focus_mask_flush(cnt, carry);
     // epilogue: lane p (p < 32) takes pair p
     int32_t mine = 0;
 #pragma unroll
-    for (int p = 0; p < P1Z_WX * P1Z_WY; ++p) mine = lane == p ? cnt[p] : mine;
-    if (lane >= P1Z_WX * P1Z_WY) return;
-    const int64_t x = xw + lane / P1Z_WY, y = yw + lane % P1Z_WY;
+    for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) mine = lane == p ? cnt[p] : mine;
+    if (lane >= Cfg::WX * Cfg::WY) return;
+    const int64_t x = xw + lane / Cfg::WY, y = yw + lane % Cfg::WY;
     if (x >= n || y >= n || x > y) return;
     const bool mirror = x != y;
     if (atomic_mode) {
@@ -774,6 +809,40 @@ __global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__
         W[x * ldw + y] = w;
         if (mirror) W[y * ldw + x] = w;
     }
+}
+
+// The single-matrix pass-1 kernel: 4 x 2 waves (16 x 16 pairs, 512 threads),
+// 4 z per lane (256 per stage), 64 KB of LDS: two workgroups per CU, whose
+// barriers are independent (PALD_P1Z_GY = 4: 16 x 32 tiles of 1024 threads,
+// one per CU, about 3 % slower).  The tiles cover every pair x <= y exactly
+// once: tile (bi, bj) spans x in [TX bi, TX bi + TX), y in [TY bj, TY bj +
+// TY), and the tiles with floor(bi / S) <= bj, S = TY / TX, are enumerated as
+// the S parts of the square TY x TY tiles bx <= bj in the grouped order of
+// grouped_tile().  blockIdx.y is the z-chunk; with one chunk the tile writes
+// U and W directly, with several it atomically adds into U (zero on entry).
+#ifndef PALD_P1Z_GY
+#define PALD_P1Z_GY 2
+#endif
+using P1zMain = P1zCfg<4, PALD_P1Z_GY, 4>;
+constexpr int P1Z_TX = P1zMain::TX, P1Z_TY = P1zMain::TY, P1Z_NT = P1zMain::NT, P1Z_ZS = P1zMain::ZS;
+constexpr int P1Z_SPLIT = P1Z_TY / P1Z_TX;  // tiles per TY x TY square
+static_assert(P1Z_SPLIT * P1Z_TX == P1Z_TY, "the y side must be a multiple of the x side");
+
+__global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__restrict__ D, int64_t n,
+                                                                 int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
+                                                                 float *__restrict__ W, int64_t ldw,
+                                                                 int32_t z_per_chunk, int32_t atomic_mode,
+                                                                 int32_t vec_ok, int32_t tile0) {
+    __shared__ uint32_t smw[P1zMain::LDS_WORDS];
+    const int32_t k = tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    int32_t bx, bj;
+    grouped_tile(k / P1Z_SPLIT, (int32_t)((n + P1Z_TY - 1) / P1Z_TY), bx, bj);
+    const int64_t X0 = (int64_t)(P1Z_SPLIT * bx + k % P1Z_SPLIT) * P1Z_TX, Y0 = (int64_t)bj * P1Z_TY;
+    if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
+    const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
+    const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
+    pass1z_tile<4, PALD_P1Z_GY, 4>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
+                                   atomic_mode != 0, vec_ok != 0);
 }
 
 // W_xy = fl32(1/U_xy) off the diagonal, 0 on it (used after a split pass 1).

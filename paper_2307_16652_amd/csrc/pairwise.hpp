@@ -812,9 +812,10 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 }
 
 // The single-matrix pass-1 kernel: 4 x 2 waves (16 x 16 pairs, 512 threads),
-// 4 z per lane (256 per stage), 64 KB of LDS: two workgroups per CU, whose
-// barriers are independent (PALD_P1Z_GY = 4: 16 x 32 tiles of 1024 threads,
-// one per CU, about 3 % slower).  The tiles cover every pair x <= y exactly
+// 2 z per lane (128 per stage), 32 KB of LDS and 73 VGPRs: three workgroups
+// per CU, 6 waves per SIMD, with independent barriers (4 z per lane: 64 KB
+// and 91 VGPRs, 4 waves per SIMD, 5 % slower; PALD_P1Z_GY = 4: 16 x 32 tiles
+// of 1024 threads, slower still).  The tiles cover every pair x <= y exactly
 // once: tile (bi, bj) spans x in [TX bi, TX bi + TX), y in [TY bj, TY bj +
 // TY), and the tiles with floor(bi / S) <= bj, S = TY / TX, are enumerated as
 // the S parts of the square TY x TY tiles bx <= bj in the grouped order of
@@ -823,12 +824,18 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 #ifndef PALD_P1Z_GY
 #define PALD_P1Z_GY 2
 #endif
-using P1zMain = P1zCfg<4, PALD_P1Z_GY, 4>;
+#ifndef PALD_P1Z_NC
+#define PALD_P1Z_NC 2
+#endif
+#ifndef PALD_P1Z_MIN_WAVES
+#define PALD_P1Z_MIN_WAVES 1
+#endif
+using P1zMain = P1zCfg<4, PALD_P1Z_GY, PALD_P1Z_NC>;
 constexpr int P1Z_TX = P1zMain::TX, P1Z_TY = P1zMain::TY, P1Z_NT = P1zMain::NT, P1Z_ZS = P1zMain::ZS;
 constexpr int P1Z_SPLIT = P1Z_TY / P1Z_TX;  // tiles per TY x TY square
 static_assert(P1Z_SPLIT * P1Z_TX == P1Z_TY, "the y side must be a multiple of the x side");
 
-__global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__restrict__ D, int64_t n,
+__global__ __launch_bounds__(P1Z_NT, PALD_P1Z_MIN_WAVES) void pass1z_focus_kernel(const float *__restrict__ D, int64_t n,
                                                                  int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
                                                                  float *__restrict__ W, int64_t ldw,
                                                                  int32_t z_per_chunk, int32_t atomic_mode,
@@ -841,7 +848,7 @@ __global__ __launch_bounds__(P1Z_NT, 1) void pass1z_focus_kernel(const float *__
     if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
-    pass1z_tile<4, PALD_P1Z_GY, 4>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
+    pass1z_tile<4, PALD_P1Z_GY, PALD_P1Z_NC>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
                                    atomic_mode != 0, vec_ok != 0);
 }
 

@@ -712,33 +712,36 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     auto run = [&](auto vec_tag) {
         constexpr bool VEC = decltype(vec_tag)::value;
         P1zStage<RPW, NC> pre;
-        auto fetch = [&](int32_t st) {  // stage st: z = zbeg + ZS st + ...
-            if (st < nst_fast) {
-                // byte offset in the row: below 4 n, and n x n floats fit in memory
-                const uint32_t off =
-                    ((uint32_t)st * Cfg::ZS + (uint32_t)NC * (uint32_t)lane) * (uint32_t)sizeof(float);
+        // stage st with no checks (st < nst_fast); `off` is its byte offset in
+        // the rows, below 4 n (and n x n floats fit in memory)
+        auto fetch_fast = [&](uint32_t off) {
 #pragma unroll
-                for (int q = 0; q < RPW; ++q) {
-                    if constexpr (!VEC) {
+            for (int q = 0; q < RPW; ++q) {
+                if constexpr (!VEC) {
 #pragma unroll
-                        for (int c = 0; c < NC; ++c)
-                            pre.r[q].v[c] = __float_as_uint(reinterpret_cast<const float *>(rowp[q] + off)[c]);
-                    } else if constexpr (NC == 4) {
-                        const float4 v = *reinterpret_cast<const float4 *>(rowp[q] + off);
-                        pre.r[q].v[0] = __float_as_uint(v.x);
-                        pre.r[q].v[1] = __float_as_uint(v.y);
-                        pre.r[q].v[2] = __float_as_uint(v.z);
-                        pre.r[q].v[3] = __float_as_uint(v.w);
-                    } else {
-                        const float2 v = *reinterpret_cast<const float2 *>(rowp[q] + off);
-                        pre.r[q].v[0] = __float_as_uint(v.x);
-                        pre.r[q].v[1] = __float_as_uint(v.y);
-                    }
+                    for (int c = 0; c < NC; ++c)
+                        pre.r[q].v[c] = __float_as_uint(reinterpret_cast<const float *>(rowp[q] + off)[c]);
+                } else if constexpr (NC == 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(rowp[q] + off);
+                    pre.r[q].v[0] = __float_as_uint(v.x);
+                    pre.r[q].v[1] = __float_as_uint(v.y);
+                    pre.r[q].v[2] = __float_as_uint(v.z);
+                    pre.r[q].v[3] = __float_as_uint(v.w);
+                } else {
+                    const float2 v = *reinterpret_cast<const float2 *>(rowp[q] + off);
+                    pre.r[q].v[0] = __float_as_uint(v.x);
+                    pre.r[q].v[1] = __float_as_uint(v.y);
                 }
-            } else {
+            }
+        };
+        constexpr uint32_t STAGE_BYTES = Cfg::ZS * sizeof(float);
+        const uint32_t lane_off = (uint32_t)NC * (uint32_t)lane * (uint32_t)sizeof(float);
+        auto fetch = [&](int32_t st) {  // stage st: z = zbeg + ZS st + ...
+            if (st < nst_fast)
+                fetch_fast((uint32_t)st * STAGE_BYTES + lane_off);
+            else
                 pre = p1z_fetch_edge<GX, GY, NC>(D, ldd, n, X0, Y0, wave, lane, zbeg + (int64_t)st * Cfg::ZS, zend,
                                                  VEC);
-            }
         };
         // LDS layout of a stage: [row][c][lane], element = z zs + NC lane + c,
         // so that the reads of one component c are contiguous over the lanes
@@ -750,17 +753,10 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
                 for (int c = 0; c < NC; ++c) dst[64 * c] = pre.r[q].v[c];
             }
         };
-
-        if (nst > 0) {
-            fetch(0);
-            stash(0);
-        }
-        __syncthreads();
-        for (int32_t st = 0; st < nst; ++st) {
-            const int buf = st & 1;
-            if (st + 1 < nst) fetch(st + 1);
-            // component c + 1 is read before the block of component c runs (the
-            // scheduling barriers keep the reads there), so that they overlap it
+        // the counting of one staged buffer: component c + 1 is read before the
+        // block of component c runs (the scheduling barriers keep the reads
+        // there), so that the reads overlap it
+        auto count = [&](int buf) {
             const uint32_t *sb = smw + buf * (Cfg::ROWS * Cfg::ZS) + lane;
             uint32_t av[2][Cfg::WX], bv[2][Cfg::WY];
             auto read_comp = [&](int c) {
@@ -777,6 +773,33 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
                 focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
                 __builtin_amdgcn_sched_barrier(0);
             }
+        };
+
+        if (nst > 0) {
+            fetch(0);
+            stash(0);
+        }
+        __syncthreads();
+        // Stages whose successor loads without checks run two at a time with
+        // fixed buffers (buffer 0 holds stage st on entry): little loop control
+        // on the scalar unit, which also does the counting.
+        int32_t st = 0;
+        uint32_t off = STAGE_BYTES + lane_off;  // of stage st + 1
+        for (; st + 2 < nst_fast; st += 2) {
+            fetch_fast(off);
+            count(0);
+            stash(1);
+            __syncthreads();
+            fetch_fast(off + STAGE_BYTES);
+            count(1);
+            stash(0);
+            __syncthreads();
+            off += 2 * STAGE_BYTES;
+        }
+        for (; st < nst; ++st) {  // the rest, buffer st & 1
+            const int buf = st & 1;
+            if (st + 1 < nst) fetch(st + 1);
+            count(buf);
             if (st + 1 < nst) stash(buf ^ 1);
             __syncthreads();
         }

@@ -119,6 +119,7 @@ def batched_bench(dev, reps: int = 3):
     mats = [synth.pairwise_distances(synth.batch_points(i, int(n))) for i, n in enumerate(ns)]
     cfg = pald.load_tuning() if hasattr(pald, "load_tuning") else None
     plan = pald.BatchPlan([int(n) for n in ns], config=cfg)
+    plan_split = bool(cfg is not None and cfg.flags & pald.BATCH_SPLIT_PASS1)
     Dp = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
     del mats
     ws = plan.workspace(dev)
@@ -137,16 +138,51 @@ def batched_bench(dev, reps: int = 3):
     batch_ms = ev0.elapsed_time(ev1) / reps
     g.close()
 
+    def timestamped(flags_off=0):
+        """Per-matrix (start, end) device times of one run of the tuned config (minus flags_off)."""
+        tcfg = pald.load_tuning(timestamps=True)
+        if tcfg is None:
+            tcfg = pald.make_batch_config(timestamps=True)
+        tcfg.flags &= ~flags_off
+        tplan = pald.BatchPlan([int(n) for n in ns], config=tcfg)
+        tws = tplan.workspace(dev)
+        tplan.run(Dp, Up, Cp, tws)
+        torch.cuda.synchronize()
+        st, en = tplan.timestamps(tws)
+        tplan.close()
+        return st, en
+
     # per-matrix latency from one run with device timestamps
-    tcfg = pald.load_tuning(timestamps=True) if hasattr(pald, "load_tuning") else \
-        pald.make_batch_config(timestamps=True)
-    tplan = pald.BatchPlan([int(n) for n in ns], config=tcfg)
-    tws = tplan.workspace(dev)
-    tplan.run(Dp, Up, Cp, tws)
-    torch.cuda.synchronize()
-    start, end = tplan.timestamps(tws)
+    start, end = timestamped()
     lat = end - start
-    tplan.close()
+
+    # the one-launch form (pass-1 items in the persistent queue): its time per
+    # batch and per-matrix latency, since the split form starts every
+    # matrix's pass 1 in the first launch
+    fused = None
+    if plan_split:
+        fcfg = pald.load_tuning()
+        fcfg.flags &= ~pald.BATCH_SPLIT_PASS1
+        fplan = pald.BatchPlan([int(n) for n in ns], config=fcfg)
+        fws = fplan.workspace(dev)
+        fplan.run(Dp, Up, Cp, fws)
+        fg = fplan.graph(Dp, Up, Cp, fws)
+        fg.launch()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fg.launch()
+        ev1.record()
+        torch.cuda.synchronize()
+        fms = ev0.elapsed_time(ev1) / reps
+        fg.close()
+        fplan.close()
+        del fws
+        fst, fen = timestamped(pald.BATCH_SPLIT_PASS1)
+        flat_ = fen - fst
+        fused = {"ms_per_batch": round(fms, 3), "matrices_per_s": round(len(ns) / (fms / 1e3), 1),
+                 "latency_us_p50": round(float(np.percentile(flat_, 50)), 1),
+                 "latency_us_p99": round(float(np.percentile(flat_, 99)), 1)}
 
     # comparator: one single-matrix call per matrix, same stream, no graph
     views = plan.unpack(Dp)
@@ -170,7 +206,7 @@ def batched_bench(dev, reps: int = 3):
         "matrices_per_s": round(len(ns) / (batch_ms / 1e3), 1),
         "ms_per_batch": round(batch_ms, 3),
         "triplet_comparisons_G_per_s": round(terms / (batch_ms / 1e3) / 1e9, 1),
-        "launch": "hipGraph replay of one reset kernel + one persistent kernel",
+        "launch": ("hipGraph replay of one reset kernel, " + ("the pass-1 launch, " if plan_split else "") + "one persistent kernel"),
         "grid_workgroups": plan.grid,
         "per_matrix_launch_ms": round(loop_ms, 3),
         "per_matrix_launch_matrices_per_s": round(len(ns) / (loop_ms / 1e3), 1),
@@ -179,6 +215,7 @@ def batched_bench(dev, reps: int = 3):
         "latency_us_p99": round(float(np.percentile(lat, 99)), 1),
         "completion_since_launch_us_p50": round(float(np.percentile(end, 50)), 1),
         "completion_since_launch_us_p99": round(float(np.percentile(end, 99)), 1),
+        "one_launch_form": fused,
     }
 
 

@@ -258,6 +258,12 @@ typedef struct pald_batch_bucket {
 
 #define PALD_BATCH_MAX_BUCKETS 8
 #define PALD_BATCH_TIMESTAMPS 1u /* record per-matrix first-start / last-end device clocks */
+/* Pass 1 of every matrix runs first, as its own launch over all 16 x 16
+ * pass-1 tiles of the batch (the single-matrix lanes-over-z tile, 6 waves per
+ * SIMD); the persistent queue then holds only pass-2 items, which never wait.
+ * Without it, pass-1 items (64 x 64 lanes-over-pairs tiles) share the queue
+ * and the persistent kernel's register budget with the pass-2 items. */
+#define PALD_BATCH_SPLIT_PASS1 2u
 
 typedef struct pald_batch_config {
     int32_t nbuckets;          /* entries used in bucket[]; 0 = the built-in tuned table */
@@ -294,8 +300,9 @@ int32_t pald_batch_grid(const pald_batch_plan *plan);
 /*
  * Runs the whole batch: U_packed (may be NULL) and C_packed from D_packed,
  * all device pointers of pald_batch_total_elements() elements.  Enqueues one
- * counter-reset kernel and one persistent kernel on `stream` (no allocation,
- * no memset node, so the pair can be captured into a hipGraph).  Calls that
+ * counter-reset kernel, with PALD_BATCH_SPLIT_PASS1 the pass-1 launch(es),
+ * and one persistent kernel on `stream` (no allocation, no memset node, so
+ * the sequence can be captured into a hipGraph).  Calls that
  * share a workspace must not overlap.  C accumulates as in pald_cohesion
  * (float32 runs, Kahan partials, float64 final reduction).
  * Errors: PALD_ERR_ARG for null plan/D/C/ws or a small/misaligned ws.
@@ -318,7 +325,9 @@ pald_status pald_batch_timestamps(const pald_batch_plan *plan, const void *ws,
  * Host only, touches no GPU: writes the queue a plan for these sizes and
  * settings would run with a persistent grid of `grid` workgroups, as 4 int32
  * per item {matrix, kind (0 = pass-1 tile, 1 = pass-2 tile), tile index,
- * y-chunk}, and per matrix its pass-1 tile count to tiles1_out (may be NULL).
+ * y-chunk}, and per matrix its pass-1 item count -- the count its pass-2
+ * items wait for; 0 with PALD_BATCH_SPLIT_PASS1 -- to tiles1_out (may be
+ * NULL).
  * Returns the number of items (writing at most `cap`), or -1 on bad arguments.
  */
 int64_t pald_batch_queue(int32_t count, const int64_t *n_host,

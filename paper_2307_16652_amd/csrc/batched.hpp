@@ -115,6 +115,37 @@ __global__ void batch_reset_kernel(uint32_t *__restrict__ ctr, int64_t nctr, uin
         }
 }
 
+// Split mode, first launch: every pass-1 tile of every matrix as one
+// workgroup of the single-matrix lanes-over-z shape (16 x 16 pairs, 512
+// threads, 6 waves per SIMD), which the persistent kernel's register budget
+// (set by its pass-2 tile) could not hold.  tiles[k] = {matrix, X0, Y0, 0} with
+// X0 <= Y0, listed largest matrix first.  Each XCD takes a contiguous run of
+// the list, so the tiles running on one XCD mostly share a matrix and its rows
+// of D in that XCD's L2.
+__device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const int4 t,
+                                                  const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+                                                  int32_t *__restrict__ U, float *__restrict__ Wr,
+                                                  uint64_t *__restrict__ stamps, int32_t d_aligned) {
+    const int32_t mi = t.x;
+    const int64_t moff = mats[mi].off, mwoff = mats[mi].woff;
+    const int64_t n = mats[mi].n, ldw = mats[mi].ldw;
+    const bool vec_d = d_aligned && mats[mi].vec_d;
+    if (stamps && tid == 0)
+        atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
+    pass1z_tile<4, PALD_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n, Wr + mwoff, ldw,
+                                             t.y, t.z, 0, n, false, vec_d);
+}
+
+// One tile per workgroup; launched in pieces of gridDim.x tiles from tile0.
+__global__ __launch_bounds__(P1Z_NT, PALD_P1Z_MIN_WAVES) void batched_focus_kernel(
+    const int4 *__restrict__ tiles, int32_t ntiles, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+    int32_t *__restrict__ U, float *__restrict__ Wr, uint64_t *__restrict__ stamps, int32_t d_aligned,
+    int32_t tile0) {
+    __shared__ uint32_t smw[P1zMain::LDS_WORDS];
+    const int32_t k = tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    batched_focus_one((int)threadIdx.x, smw, tiles[k], mats, D, U, Wr, stamps, d_aligned);
+}
+
 __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_cohesion_kernel(
     const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     int32_t *__restrict__ U, float *__restrict__ C, float *__restrict__ Wr, double *__restrict__ Pr,

@@ -683,12 +683,22 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     uint32_t t[Cfg::WX * Cfg::WY];
     int32_t cnt[Cfg::WX * Cfg::WY];
     uint64_t carry[2] = {0, 0};
+    // (clamped addresses and no branch per value, so that all the scalar
+    // loads are in flight at once; the values of pairs outside the matrix are
+    // replaced by 0 afterwards and never written)
+    uint32_t tv[Cfg::WX * Cfg::WY];
+    const int32_t nm1 = (int32_t)(n - 1), xw32 = (int32_t)xw, yw32 = (int32_t)yw;  // indices < n < 2^31
+#pragma unroll
+    for (int i = 0; i < Cfg::WX; ++i) {
+        const float *row = D + (int64_t)min(xw32 + i, nm1) * ldd;
+#pragma unroll
+        for (int j = 0; j < Cfg::WY; ++j) tv[i * Cfg::WY + j] = __float_as_uint(row[min(yw32 + j, nm1)]);
+    }
 #pragma unroll
     for (int i = 0; i < Cfg::WX; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::WY; ++j) {
-            const int64_t x = xw + i, y = yw + j;
-            uint32_t v = (x < n && y < n) ? __float_as_uint(D[x * ldd + y]) : 0u;
+            const uint32_t v = (xw32 + i <= nm1 && yw32 + j <= nm1) ? tv[i * Cfg::WY + j] : 0u;
             asm volatile("v_mov_b32 %0, %1" : "=v"(t[i * Cfg::WY + j]) : "s"(v));
             cnt[i * Cfg::WY + j] = 0;
         }

@@ -421,6 +421,7 @@ constexpr int kDefaultLag = 2;
 struct BatchLayout {
     std::vector<BatchMatrix> mats;
     std::vector<int4> items;
+    std::vector<int4> tiles1z;  // PALD_BATCH_SPLIT_PASS1: {matrix, X0, Y0, 0} of every pass-1 tile
     std::vector<int64_t> n, off;
     int64_t total_elems = 0;
     int64_t w_floats = 0;     // weight region size (floats)
@@ -431,7 +432,7 @@ struct BatchLayout {
 pald_status check_config(const pald_batch_config *cfg) {
     if (!cfg) return PALD_OK;
     if (cfg->nbuckets < 0 || cfg->nbuckets > PALD_BATCH_MAX_BUCKETS || cfg->workgroups_per_cu < 0 ||
-        cfg->queue_lag < 0 || (cfg->flags & ~PALD_BATCH_TIMESTAMPS))
+        cfg->queue_lag < 0 || (cfg->flags & ~(PALD_BATCH_TIMESTAMPS | PALD_BATCH_SPLIT_PASS1)))
         return PALD_ERR_ARG;
     for (int b = 0; b < cfg->nbuckets; ++b) {
         const pald_batch_bucket &k = cfg->bucket[b];
@@ -461,6 +462,7 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
     if (count < 1 || !n_host || grid < 1) return PALD_ERR_ARG;
     if (pald_status st = check_config(cfg); st != PALD_OK) return st;
     L = BatchLayout{};
+    const bool split = cfg && (cfg->flags & PALD_BATCH_SPLIT_PASS1);
     L.mats.resize(count);
     L.n.assign(n_host, n_host + count);
     L.off.resize(count);
@@ -476,7 +478,7 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
         m.ldw = (int32_t)align_up((size_t)n, 4);
         m.woff = woff;
         const int64_t nb1 = ceil_div(n, BATCH_P1_T);
-        m.tiles1 = (int32_t)(nb1 * (nb1 + 1) / 2);
+        m.tiles1 = split ? 0 : (int32_t)(nb1 * (nb1 + 1) / 2);
         const int64_t T2 = bk.tile ? bk.tile : BATCH_P2_T;
         m.tile2 = (int32_t)T2;
         const int64_t nb2 = ceil_div(n, T2);
@@ -512,6 +514,23 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
         for (int64_t t = 0; t < tiles2; ++t)
             for (int32_t c = 0; c < m.y_chunks; ++c) L.items.push_back(make_int4(i, ITEM_PASS2, (int)t, c));
     };
+    if (split) {
+        // pass-1 tiles of the first launch, largest matrix first; inside a
+        // matrix the 16 x 16 tiles x <= y by groups of G x G (as grouped_tile)
+        constexpr int64_t G = TILE_GROUP;
+        for (int32_t i : order) {
+            const int64_t n = L.n[i], nb = ceil_div(n, (int64_t)P1Z_TX), nsb = ceil_div(nb, G);
+            for (int64_t gy = 0; gy < nsb; ++gy)
+                for (int64_t gx = 0; gx <= gy; ++gx)
+                    for (int64_t by = gy * G; by < std::min(nb, gy * G + G); ++by)
+                        for (int64_t bx = gx * G; bx < std::min(nb, gx * G + G) && bx <= by; ++bx)
+                            L.tiles1z.push_back(make_int4(i, (int)(bx * P1Z_TX), (int)(by * P1Z_TX), 0));
+            if (L.tiles1z.size() > (size_t)INT32_MAX) return PALD_ERR_UNSUPPORTED;
+        }
+        for (int32_t i : order) emit_p2(i);
+        if (L.items.size() > (size_t)INT32_MAX) return PALD_ERR_UNSUPPORTED;
+        return PALD_OK;
+    }
     std::vector<std::pair<int32_t, int64_t>> pending;  // (matrix, queue position after its last pass-1 item)
     size_t head = 0;
     int64_t p1_emitted = 0;
@@ -551,6 +570,7 @@ struct pald_batch_plan {
     BatchLayout L;
     BatchMatrix *d_mats = nullptr;
     int4 *d_items = nullptr;
+    int4 *d_tiles1z = nullptr;
     size_t off_w = 0, off_p = 0, off_ctr = 0, off_stamps = 0, ws_bytes = 0;
 };
 
@@ -560,6 +580,8 @@ struct pald_batch_graph {
 };
 
 namespace {
+
+constexpr int64_t kMaxGrid1 = (int64_t)1 << 22;  // pass-1 tiles per launch of the split mode
 
 pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *U, float *C, void *ws,
                           hipStream_t s) {
@@ -573,6 +595,13 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
     const unsigned rg = (unsigned)std::min<int64_t>(ceil_div(nreset, 256), 1024);
     batch_reset_kernel<<<rg, 256, 0, s>>>(ctr, plan->L.nctr, stamps, plan->count);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
+    const int64_t ntiles1 = (int64_t)plan->L.tiles1z.size();
+        for (int64_t t0 = 0; t0 < ntiles1; t0 += kMaxGrid1) {
+            const int64_t nt = std::min<int64_t>(kMaxGrid1, ntiles1 - t0);
+            batched_focus_kernel<<<(unsigned)nt, P1Z_NT, 0, s>>>(plan->d_tiles1z, (int32_t)ntiles1, plan->d_mats, D,
+                                                                  U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
+            if (pald_status st = launch_status(); st != PALD_OK) return st;
+        }
     batched_cohesion_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
         plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, U, C, Wr, Pr, ctr, plan->count, stamps,
         aligned16(D) ? 1 : 0);
@@ -615,12 +644,15 @@ pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const p
     if (p->flags & PALD_BATCH_TIMESTAMPS) off = align_up(off + (size_t)count * 2 * sizeof(uint64_t), ALIGN);
     p->ws_bytes = off;
     const size_t mbytes = p->L.mats.size() * sizeof(BatchMatrix), ibytes = p->L.items.size() * sizeof(int4);
-    if (hipMalloc((void **)&p->d_mats, mbytes) != hipSuccess || hipMalloc((void **)&p->d_items, ibytes) != hipSuccess) {
+    const size_t tbytes = p->L.tiles1z.size() * sizeof(int4);
+    if (hipMalloc((void **)&p->d_mats, mbytes) != hipSuccess || hipMalloc((void **)&p->d_items, ibytes) != hipSuccess ||
+        (tbytes && hipMalloc((void **)&p->d_tiles1z, tbytes) != hipSuccess)) {
         pald_batch_plan_destroy(p);
         return PALD_ERR_NOMEM;
     }
     if (hipMemcpy(p->d_mats, p->L.mats.data(), mbytes, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_items, p->L.items.data(), ibytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(p->d_items, p->L.items.data(), ibytes, hipMemcpyHostToDevice) != hipSuccess ||
+        (tbytes && hipMemcpy(p->d_tiles1z, p->L.tiles1z.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess)) {
         pald_batch_plan_destroy(p);
         return PALD_ERR_DEVICE;
     }
@@ -691,6 +723,7 @@ void pald_batch_plan_destroy(pald_batch_plan *plan) {
     if (!plan) return;
     if (plan->d_mats) (void)hipFree(plan->d_mats);
     if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_tiles1z) (void)hipFree(plan->d_tiles1z);
     delete plan;
 }
 

@@ -40,6 +40,7 @@ EXPORTED = (
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
+BATCH_SPLIT_PASS1 = 2
 
 
 class PaldError(RuntimeError):
@@ -71,9 +72,10 @@ class BatchConfig(ctypes.Structure):
 
 
 def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int = 0,
-                      timestamps: bool = False) -> BatchConfig:
+                      timestamps: bool = False, split_pass1: bool = False) -> BatchConfig:
     """buckets: list of (n_max, y_chunks) or (n_max, y_chunks, tile) tuples, or dicts with keys
-    n_max / y_chunks / tile (tile = pass-2 tile side, 64 or 32; default 64)."""
+    n_max / y_chunks / tile (tile = pass-2 tile side, 64 or 32; default 64).  split_pass1:
+    pass 1 of every matrix as a launch of its own before the persistent kernel."""
     c = BatchConfig()
     buckets = list(buckets or [])
     if len(buckets) > BATCH_MAX_BUCKETS:
@@ -90,7 +92,7 @@ def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int =
     c.nbuckets = len(buckets)
     c.workgroups_per_cu = int(workgroups_per_cu)
     c.queue_lag = int(queue_lag)
-    c.flags = BATCH_TIMESTAMPS if timestamps else 0
+    c.flags = (BATCH_TIMESTAMPS if timestamps else 0) | (BATCH_SPLIT_PASS1 if split_pass1 else 0)
     return c
 
 
@@ -131,7 +133,7 @@ def load_tuning(path: str | None = None, timestamps: bool = False) -> BatchConfi
     with open(p) as f:
         data = json.load(f)
     return make_batch_config(data.get("buckets"), data.get("workgroups_per_cu", 0), data.get("queue_lag", 0),
-                             timestamps)
+                             timestamps, bool(data.get("split_pass1", False)))
 
 
 _lib = None

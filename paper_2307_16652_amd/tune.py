@@ -11,8 +11,11 @@ clusters in R^4), for
   staged row over more pairs),
 * the pass-2 y-split depth of each size bucket (splitting a large matrix's
   pass-2 tiles over y shortens the items at the end of the queue),
-* the persistent grid size (workgroups per CU), and
-* the queue lag (how far a matrix's pass-2 items trail its pass-1 items),
+* the persistent grid size (workgroups per CU),
+* the queue lag (how far a matrix's pass-2 items trail its pass-1 items), and
+* whether pass 1 runs inside the persistent kernel or as a launch of its own
+  ahead of it (split mode: 16 x 16 lanes-over-z tiles at 6 waves per SIMD,
+  and a queue of pass-2 items only),
 
 by coordinate descent on the measured time of one whole batched launch
 (median of `reps` graph replays), and writes the winner to
@@ -92,10 +95,10 @@ class Batch:
             plan.close()
 
 
-def config_of(pald, chunks, wpc, lag, tiles=None):
+def config_of(pald, chunks, wpc, lag, tiles=None, split=False):
     tiles = tiles or [64] * len(BUCKETS)
     return pald.make_batch_config([(b, c, t) for b, c, t in zip(BUCKETS, chunks, tiles)], workgroups_per_cu=wpc,
-                                  queue_lag=lag)
+                                  queue_lag=lag, split_pass1=split)
 
 
 def tune(reps: int = 3, out: str | None = None) -> dict:
@@ -108,40 +111,43 @@ def tune(reps: int = 3, out: str | None = None) -> dict:
     batch = Batch(dev)
     chunks = [1] * len(BUCKETS)
     tiles = [64] * len(BUCKETS)
-    wpc, lag = 0, 0
-    best = batch.time(config_of(pald, chunks, wpc, lag, tiles), reps)
+    wpc, lag, split = 0, 0, False
+    best = batch.time(config_of(pald, chunks, wpc, lag, tiles, split), reps)
     log(f"defaults: {best:.3f} ms")
-    trials = [{"chunks": list(chunks), "tiles": list(tiles), "wpc": wpc, "lag": lag, "ms": best}]
+    trials = [{"chunks": list(chunks), "tiles": list(tiles), "wpc": wpc, "lag": lag, "split_pass1": split,
+               "ms": best}]
 
-    def consider(c, t, w, l):
-        nonlocal best, chunks, tiles, wpc, lag
-        ms = batch.time(config_of(pald, c, w, l, t), reps)
-        trials.append({"chunks": list(c), "tiles": list(t), "wpc": w, "lag": l, "ms": ms})
-        log(f"chunks={c} tiles={t} wpc={w} lag={l}: {ms:.3f} ms")
+    def consider(c, t, w, l, sp):
+        nonlocal best, chunks, tiles, wpc, lag, split
+        ms = batch.time(config_of(pald, c, w, l, t, sp), reps)
+        trials.append({"chunks": list(c), "tiles": list(t), "wpc": w, "lag": l, "split_pass1": sp, "ms": ms})
+        log(f"chunks={c} tiles={t} wpc={w} lag={l} split={sp}: {ms:.3f} ms")
         if ms < best * 0.995:
-            best, chunks, tiles, wpc, lag = ms, list(c), list(t), w, l
+            best, chunks, tiles, wpc, lag, split = ms, list(c), list(t), w, l, sp
 
+    consider(chunks, tiles, wpc, lag, True)
     for w in WPC:
-        for l in LAGS:
-            consider(chunks, tiles, w, l)
+        for l in (LAGS if not split else (0,)):  # the lag only matters with pass-1 items in the queue
+            consider(chunks, tiles, w, l, split)
     for _ in range(2):  # two sweeps of coordinate descent over the buckets
         for b in reversed(range(len(BUCKETS))):
             for tl in TILES:
                 if tl != tiles[b]:
                     cand = list(tiles)
                     cand[b] = tl
-                    consider(chunks, cand, wpc, lag)
+                    consider(chunks, cand, wpc, lag, split)
             for c in Y_CHUNKS:
                 if c != chunks[b]:
                     cand = list(chunks)
                     cand[b] = c
-                    consider(cand, tiles, wpc, lag)
+                    consider(cand, tiles, wpc, lag, split)
     result = {
         "arch": "gfx950",
         "workload": "2000 matrices, n uniform in [32, 1024], 2-5 Gaussian clusters in R^4, seed 4",
         "buckets": [{"n_max": b, "y_chunks": c, "tile": t} for b, c, t in zip(BUCKETS, chunks, tiles)],
         "workgroups_per_cu": wpc,
         "queue_lag": lag,
+        "split_pass1": split,
         "ms_per_batch": round(best, 3),
         "default_ms_per_batch": round(trials[0]["ms"], 3),
         "trials": trials,

@@ -19,7 +19,9 @@ def simulate(items, tiles1, workers, rng):
     """Returns (finish time, number of items run). Raises on deadlock or order violation."""
     nmat = len(tiles1)
     done1 = np.zeros(nmat, dtype=np.int64)
-    p1_finished_at = [None] * nmat
+    # a matrix whose pass-2 items wait for no pass-1 item had its pass 1 done
+    # before the persistent launch (split mode)
+    p1_finished_at = [0.0 if tiles1[m] == 0 else None for m in range(nmat)]
     head = 0
     t = 0.0
     running = []  # (finish_time, worker, item index)
@@ -130,6 +132,23 @@ def test_pass2_tile_side_per_bucket(tile):
     assert ran == len(items)
 
 
+@pytest.mark.parametrize("mix", sorted(SIZE_MIXES))
+def test_split_pass1_queue(mix):
+    """With pass 1 split into its own launch the queue holds every pass-2 item once,
+    largest matrices first, and no item waits (every pass-1 count is 0)."""
+    sizes = SIZE_MIXES[mix]
+    cfg = pald.make_batch_config([(128, 1), (1 << 30, 3)], split_pass1=True)
+    items, tiles1 = pald.batch_queue(sizes, grid=64, config=cfg)
+    fused, _ = pald.batch_queue(sizes, grid=64, config=pald.make_batch_config([(128, 1), (1 << 30, 3)]))
+    assert (items[:, 1] == 1).all() and (tiles1 == 0).all()
+    assert {tuple(r) for r in items.tolist()} == {tuple(r) for r in fused[fused[:, 1] == 1].tolist()}
+    assert len({tuple(r) for r in items.tolist()}) == len(items)
+    order = [sizes[m] for m in items[:, 0]]
+    assert all(a >= b for a, b in zip(order, order[1:])), "not largest matrix first"
+    _, ran = simulate(items, tiles1, 7, np.random.default_rng(5))
+    assert ran == len(items)
+
+
 def test_y_split_items():
     cfg = pald.make_batch_config([(100, 1), (1 << 30, 4)])
     items, _ = pald.batch_queue([90, 300], grid=8, config=cfg)
@@ -167,6 +186,7 @@ def test_tuning_table_loads_into_a_valid_config():
         return
     assert cfg is not None and 1 <= cfg.nbuckets <= pald.BATCH_MAX_BUCKETS
     items, tiles1 = pald.batch_queue([40, 300, 1000], grid=512, config=cfg)
-    assert len(items) > 0 and (tiles1 > 0).all()
+    split = bool(cfg.flags & pald.BATCH_SPLIT_PASS1)
+    assert len(items) > 0 and ((tiles1 == 0).all() if split else (tiles1 > 0).all())
     tcfg = pald.load_tuning(timestamps=True)
-    assert tcfg.flags == pald.BATCH_TIMESTAMPS
+    assert tcfg.flags == pald.BATCH_TIMESTAMPS | (pald.BATCH_SPLIT_PASS1 if split else 0)

@@ -202,6 +202,62 @@ def test_unaligned_base_pointer():
               what="unaligned")
 
 
+@pytest.mark.parametrize("tile,chunks", [(64, 1), (32, 1), (64, 3)])
+def test_split_pass1(tile, chunks):
+    """Pass 1 as its own launch of 16 x 16 lanes-over-z tiles: oracle parity on
+    ragged and tie-heavy sizes, and U and C bit-identical to the one-launch mode
+    (the weights are the same fl32(1/U) and pass 2 is the same code)."""
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch(RAGGED, seed=13) + make_batch([4, 40, 96, 161], seed=14, kind="grid")
+    buckets = [(100, 1, tile), (1 << 30, chunks, tile)]
+    log(f"[batched] split pass 1, tile {tile}, y_chunks {chunks}")
+    _, _, Us, Cs = run_batch(mats, config=pald.make_batch_config(buckets, split_pass1=True))
+    check_all(mats, Us, Cs, what=f"split tile {tile} y_chunks={chunks}")
+    _, _, Uf, Cf = run_batch(mats, config=pald.make_batch_config(buckets))
+    for i in range(len(mats)):
+        assert np.array_equal(Us[i], Uf[i]), f"matrix {i}: U differs between the modes"
+        assert np.array_equal(Cs[i].view(np.int32), Cf[i].view(np.int32)), f"matrix {i}: C differs"
+
+
+def test_split_pass1_graph_timestamps_unaligned_no_u():
+    """Split mode: graph replays with eager work between them, timestamps, a packed
+    base 4 bytes past an aligned address, and no U output."""
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([77, 150, 3, 64, 201, 36], seed=15)
+    cfg = pald.make_batch_config([(100, 1), (1 << 30, 2)], timestamps=True, split_pass1=True)
+    plan = pald.BatchPlan([m.shape[0] for m in mats], config=cfg)
+    flat = np.concatenate([m.reshape(-1) for m in mats])
+    buf = torch.zeros(flat.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(flat).cuda()
+    Dp = buf[1:]
+    ws = plan.workspace(Dp.device)
+    U1, C1 = plan.run(Dp, ws=ws)
+    U1, C1 = U1.clone(), C1.clone()
+    torch.cuda.synchronize()
+    start, end = plan.timestamps(ws)
+    assert (start >= 0).all() and (end > start).all() and start.min() == 0
+    check_all(mats, [u.cpu().numpy() for u in plan.unpack(U1)], [c.cpu().numpy() for c in plan.unpack(C1)],
+              what="split unaligned")
+    g = plan.graph(Dp)
+    for r in range(3):
+        g.C.fill_(-1.0)
+        g.U.fill_(-1)
+        torch.cuda.synchronize()
+        Ug, Cg = g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, U1) and torch.equal(Cg, C1), f"split graph replay {r} differs"
+        plan.run(Dp, ws=ws)
+        torch.cuda.synchronize()
+    g.close()
+    _, C0 = plan.run(Dp, ws=ws, want_u=False)
+    torch.cuda.synchronize()
+    assert torch.equal(C0, C1)
+
+
 def test_config_batch_2000_sampled():
     """The 2000-matrix workload (n uniform in [32, 1024], 2-5 clusters in R^4):
     oracle on every 20th matrix, invariants on all."""
@@ -211,7 +267,9 @@ def test_config_batch_2000_sampled():
     ns = synth.batch_sizes()
     mats = [synth.pairwise_distances(synth.batch_points(i, int(n))) for i, n in enumerate(ns)]
     log(f"[batched] generated 2000 matrices in {time.time() - t0:.1f}s")
-    _, _, Us, Cs = run_batch(mats)
+    from paper_2307_16652_amd import pald
+
+    _, _, Us, Cs = run_batch(mats, config=pald.load_tuning())  # the benchmark's configuration
     log("[batched] run done; checking")
     check_all(mats, Us, Cs, every=20, what="batch2000")
     for i in range(len(mats)):

@@ -106,7 +106,7 @@ def error_stats(C_rows: np.ndarray, Co: np.ndarray) -> dict:
             "exact_zeros_ok": bool((C_rows[~nz] == 0).all())}
 
 
-def batched_bench(dev, reps: int = 3):
+def batched_bench(dev, reps: int = 3, one_launch_form: bool = True):
     """The 2000-matrix batch (n uniform in [32, 1024]): one persistent launch per
     batch, replayed from a captured hipGraph, against the same library's
     single-matrix path launched once per matrix on one stream."""
@@ -160,7 +160,7 @@ def batched_bench(dev, reps: int = 3):
     # batch and per-matrix latency, since the split form starts every
     # matrix's pass 1 in the first launch
     fused = None
-    if plan_split:
+    if plan_split and one_launch_form:
         fcfg = pald.load_tuning()
         fcfg.flags &= ~pald.BATCH_SPLIT_PASS1
         fplan = pald.BatchPlan([int(n) for n in ns], config=fcfg)
@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 2000-matrix batched measurement")
+    ap.add_argument("--no-one-launch-form", action="store_true",
+                    help="batched: skip timing the one-launch form beside the tuned split form")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the distance front end, local depths and strong-tie measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -475,7 +477,7 @@ def main():
     if not args.no_batched:
         del U, C, ws
         torch.cuda.empty_cache()
-        extra["batched"] = batched_bench(dev)
+        extra["batched"] = batched_bench(dev, one_launch_form=not args.no_one_launch_form)
         progress(f"batched: {extra['batched']}")
 
     out = {

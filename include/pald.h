@@ -234,7 +234,9 @@ pald_status pald_strong_ties(const float *C, int64_t n, int64_t ldc, float thres
 
 /*
  * Batched mode: many independent matrices of different sizes in one
- * persistent launch (no batching in the paper; a GPU-side extension).
+ * persistent launch, or with PALD_BATCH_SPLIT_PASS1 one launch over every
+ * matrix's pass-1 tiles followed by the persistent launch (no batching in the
+ * paper; a GPU-side extension).
  *
  * Packed layout: matrix i has n_i rows, leading dimension n_i, and starts at
  * element offset off_i = sum_{j<i} n_j^2 of D_packed, U_packed and C_packed.
@@ -243,7 +245,9 @@ pald_status pald_strong_ties(const float *C, int64_t n, int64_t ldc, float thres
  * every matrix is one item; matrices are taken largest first, and the pass-2
  * items of a matrix are placed `queue_lag` grid-sizes of items after its last
  * pass-1 item.  All pass-1 items of a matrix precede its pass-2 items, which
- * is what makes the in-kernel wait of a pass-2 item always terminate.
+ * is what makes the in-kernel wait of a pass-2 item always terminate.  In
+ * split mode the queue holds the pass-2 items only (largest matrix first) and
+ * no item waits.
  */
 typedef struct pald_batch_plan pald_batch_plan;
 

@@ -83,10 +83,10 @@ constexpr int BATCH_P2S_T = 32, BATCH_P2S_RX = BATCH_THREADS == 256 ? 1 : 0;
 using BatchP2S = Pass2Cfg<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY>;
 static_assert(BatchP1::NT == BATCH_THREADS && BatchP2::NT == BATCH_THREADS && BatchP2S::NT == BATCH_THREADS,
               "all batched tile shapes use one workgroup size");
-// Pass-1 items (64 x 64 pair regions) run as 8 x 16 lanes-over-z tiles
-// (2 x 2 waves of 4 x 8 pairs, 2 z per lane and 128 z per stage: short
-// matrices waste less of their last stage) when PALD_BATCH_P1_LANES_Z = 1
-// (default), else as one lanes-over-pairs pass1_tile.
+// Pass-1 items (64 x 64 pair regions) run as one lanes-over-pairs pass1_tile
+// (default), or with PALD_BATCH_P1_LANES_Z = 1 as 8 x 16 lanes-over-z tiles
+// (2 x 2 waves of 4 x 8 pairs, 2 z per lane and 128 z per stage), which are
+// slower here at the kernel's 3 waves per SIMD.
 #ifndef PALD_BATCH_P1_LANES_Z
 #define PALD_BATCH_P1_LANES_Z 0
 #endif

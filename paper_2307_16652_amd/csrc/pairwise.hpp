@@ -683,25 +683,28 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     uint32_t t[Cfg::WX * Cfg::WY];
     int32_t cnt[Cfg::WX * Cfg::WY];
     uint64_t carry[2] = {0, 0};
-    // (clamped addresses and no branch per value, so that all the scalar
-    // loads are in flight at once; the values of pairs outside the matrix are
-    // replaced by 0 afterwards and never written)
-    uint32_t tv[Cfg::WX * Cfg::WY];
-    const int32_t nm1 = (int32_t)(n - 1), xw32 = (int32_t)xw, yw32 = (int32_t)yw;  // indices < n < 2^31
-#pragma unroll
-    for (int i = 0; i < Cfg::WX; ++i) {
-        const float *row = D + (int64_t)min(xw32 + i, nm1) * ldd;
-#pragma unroll
-        for (int j = 0; j < Cfg::WY; ++j) tv[i * Cfg::WY + j] = __float_as_uint(row[min(yw32 + j, nm1)]);
-    }
-#pragma unroll
-    for (int i = 0; i < Cfg::WX; ++i)
-#pragma unroll
-        for (int j = 0; j < Cfg::WY; ++j) {
-            const uint32_t v = (xw32 + i <= nm1 && yw32 + j <= nm1) ? tv[i * Cfg::WY + j] : 0u;
-            asm volatile("v_mov_b32 %0, %1" : "=v"(t[i * Cfg::WY + j]) : "s"(v));
-            cnt[i * Cfg::WY + j] = 0;
+    static_assert(Cfg::NW * Cfg::WX * Cfg::WY <= Cfg::ROWS * Cfg::ZS, "the keys fit in one stage buffer");
+    // Lane p < 32 loads the key of pair p (row and column clamped into the
+    // matrix: a pair outside it is counted but never written) and the wave
+    // passes the 32 keys to every lane through LDS: one vector load and a few
+    // LDS instructions instead of 32 scalar loads and their 64-bit address
+    // arithmetic on the scalar unit, which also does the counting (per tile
+    // and wave, 213 scalar instructions before the stage loop instead of
+    // 508).  The keys sit in the second stage buffer, which the first stage
+    // leaves alone and the stage loop first writes after a barrier.
+    {
+        uint32_t *kw = smw + Cfg::ROWS * Cfg::ZS + wave * (Cfg::WX * Cfg::WY);
+        if (lane < Cfg::WX * Cfg::WY) {
+            const int64_t x = min(xw + lane / Cfg::WY, n - 1), y = min(yw + lane % Cfg::WY, n - 1);
+            kw[lane] = __float_as_uint(D[x * ldd + y]);
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) {
+            t[p] = kw[p];
+            cnt[p] = 0;
+        }
+    }
 
     const int32_t nst = (int32_t)((zend - zbeg + Cfg::ZS - 1) / Cfg::ZS);
     // Stages that lie inside [zbeg, zend) of a tile whose rows all exist load
@@ -715,7 +718,12 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     for (int q = 0; q < RPW; ++q) {
         const int r = wave + q * Cfg::NW;
         const int64_t row = r < Cfg::TX ? X0 + r : Y0 + (r - Cfg::TX);
-        rowp[q] = reinterpret_cast<const char *>(D + min(row, n - 1) * ldd + zbeg);
+        // (the byte offset made explicitly wave-uniform, so that the row
+        // pointers stay in scalar registers)
+        const uint64_t ro = (uint64_t)(min(row, n - 1) * ldd + zbeg) * sizeof(float);
+        rowp[q] = reinterpret_cast<const char *>(D) +
+                  (((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(ro >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)ro));
     }
     // The stage loop, instantiated for aligned rows (VEC: vector loads) and for
     // unaligned ones (one load per value); one tile runs one of the two.

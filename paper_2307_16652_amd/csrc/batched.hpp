@@ -132,7 +132,7 @@ __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const 
     const bool vec_d = d_aligned && mats[mi].vec_d;
     if (stamps && tid == 0)
         atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
-    pass1z_tile<4, PALD_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n, Wr + mwoff, ldw,
+    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n, Wr + mwoff, ldw,
                                              t.y, t.z, 0, n, false, vec_d);
 }
 

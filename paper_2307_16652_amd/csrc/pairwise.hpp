@@ -862,6 +862,9 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 // the S parts of the square TY x TY tiles bx <= bj in the grouped order of
 // grouped_tile().  blockIdx.y is the z-chunk; with one chunk the tile writes
 // U and W directly, with several it atomically adds into U (zero on entry).
+#ifndef PALD_P1Z_GX
+#define PALD_P1Z_GX 4
+#endif
 #ifndef PALD_P1Z_GY
 #define PALD_P1Z_GY 2
 #endif
@@ -871,7 +874,7 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 #ifndef PALD_P1Z_MIN_WAVES
 #define PALD_P1Z_MIN_WAVES 1
 #endif
-using P1zMain = P1zCfg<4, PALD_P1Z_GY, PALD_P1Z_NC>;
+using P1zMain = P1zCfg<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>;
 constexpr int P1Z_TX = P1zMain::TX, P1Z_TY = P1zMain::TY, P1Z_NT = P1zMain::NT, P1Z_ZS = P1zMain::ZS;
 constexpr int P1Z_SPLIT = P1Z_TY / P1Z_TX;  // tiles per TY x TY square
 static_assert(P1Z_SPLIT * P1Z_TX == P1Z_TY, "the y side must be a multiple of the x side");
@@ -889,7 +892,7 @@ __global__ __launch_bounds__(P1Z_NT, PALD_P1Z_MIN_WAVES) void pass1z_focus_kerne
     if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
-    pass1z_tile<4, PALD_P1Z_GY, PALD_P1Z_NC>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
+    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
                                    atomic_mode != 0, vec_ok != 0);
 }
 

@@ -518,6 +518,7 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
         // pass-1 tiles of the first launch, largest matrix first; inside a
         // matrix the 16 x 16 tiles x <= y by groups of G x G (as grouped_tile)
         constexpr int64_t G = TILE_GROUP;
+        static_assert(P1Z_TX == P1Z_TY, "the batched pass-1 list enumerates square tiles");
         for (int32_t i : order) {
             const int64_t n = L.n[i], nb = ceil_div(n, (int64_t)P1Z_TX), nsb = ceil_div(nb, G);
             for (int64_t gy = 0; gy < nsb; ++gy)

@@ -116,12 +116,26 @@ __global__ void batch_reset_kernel(uint32_t *__restrict__ ctr, int64_t nctr, uin
 }
 
 // Split mode, first launch: every pass-1 tile of every matrix as one
-// workgroup of the single-matrix lanes-over-z shape (16 x 16 pairs, 512
-// threads, 6 waves per SIMD), which the persistent kernel's register budget
-// (set by its pass-2 tile) could not hold.  tiles[k] = {matrix, X0, Y0, 0} with
-// X0 <= Y0, listed largest matrix first.  Each XCD takes a contiguous run of
-// the list, so the tiles running on one XCD mostly share a matrix and its rows
-// of D in that XCD's L2.
+// workgroup of the single-matrix lanes-over-z tile (6 waves per SIMD), which
+// the persistent kernel's register budget (set by its pass-2 tile) could not
+// hold.  tiles[k] = {matrix, X0, Y0, 0}: the tiles of the upper-triangular
+// TY x TY squares, listed largest matrix first.  Each XCD takes a contiguous
+// run of the list, so the tiles running on one XCD mostly share a matrix and
+// its rows of D in that XCD's L2.
+// The tile is 8 x 16 pairs of 4 waves (256 threads, compiled for 6 waves
+// per SIMD: 6 workgroups per CU), so that a CU holds more tiles whose
+// start-up overlaps the others' counting (121.7 ms per 2000-matrix batch
+// against 122.4 with the single-matrix 16 x 16 tile of 8 waves).
+#ifndef PALD_BATCH_P1Z_GX
+#define PALD_BATCH_P1Z_GX 2
+#endif
+#ifndef PALD_BATCH_P1Z_GY
+#define PALD_BATCH_P1Z_GY 2
+#endif
+#ifndef PALD_BATCH_P1Z_MIN_WAVES
+#define PALD_BATCH_P1Z_MIN_WAVES 6
+#endif
+using BatchFocusCfg = P1zCfg<PALD_BATCH_P1Z_GX, PALD_BATCH_P1Z_GY, PALD_P1Z_NC>;
 __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const int4 t,
                                                   const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
                                                   int32_t *__restrict__ U, float *__restrict__ Wr,
@@ -132,16 +146,16 @@ __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const 
     const bool vec_d = d_aligned && mats[mi].vec_d;
     if (stamps && tid == 0)
         atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
-    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n, Wr + mwoff, ldw,
-                                             t.y, t.z, 0, n, false, vec_d);
+    pass1z_tile<PALD_BATCH_P1Z_GX, PALD_BATCH_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n,
+                                                                 Wr + mwoff, ldw, t.y, t.z, 0, n, false, vec_d);
 }
 
 // One tile per workgroup; launched in pieces of gridDim.x tiles from tile0.
-__global__ __launch_bounds__(P1Z_NT, PALD_P1Z_MIN_WAVES) void batched_focus_kernel(
+__global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void batched_focus_kernel(
     const int4 *__restrict__ tiles, int32_t ntiles, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     int32_t *__restrict__ U, float *__restrict__ Wr, uint64_t *__restrict__ stamps, int32_t d_aligned,
     int32_t tile0) {
-    __shared__ uint32_t smw[P1zMain::LDS_WORDS];
+    __shared__ uint32_t smw[BatchFocusCfg::LDS_WORDS];
     const int32_t k = tile0 + xcd_order((int32_t)blockIdx.x, (int32_t)gridDim.x);
     batched_focus_one((int)threadIdx.x, smw, tiles[k], mats, D, U, Wr, stamps, d_aligned);
 }

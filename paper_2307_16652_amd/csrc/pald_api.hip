@@ -517,15 +517,16 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
     if (split) {
         // pass-1 tiles of the first launch, largest matrix first; inside a
         // matrix the 16 x 16 tiles x <= y by groups of G x G (as grouped_tile)
-        constexpr int64_t G = TILE_GROUP;
-        static_assert(P1Z_TX == P1Z_TY, "the batched pass-1 list enumerates square tiles");
+        constexpr int64_t G = TILE_GROUP, TX = BatchFocusCfg::TX, TY = BatchFocusCfg::TY, S = TY / TX;
+        static_assert(S * TX == TY, "a TY x TY square splits into whole tiles along x");
         for (int32_t i : order) {
-            const int64_t n = L.n[i], nb = ceil_div(n, (int64_t)P1Z_TX), nsb = ceil_div(nb, G);
+            const int64_t n = L.n[i], nb = ceil_div(n, TY), nsb = ceil_div(nb, G);
             for (int64_t gy = 0; gy < nsb; ++gy)
                 for (int64_t gx = 0; gx <= gy; ++gx)
                     for (int64_t by = gy * G; by < std::min(nb, gy * G + G); ++by)
                         for (int64_t bx = gx * G; bx < std::min(nb, gx * G + G) && bx <= by; ++bx)
-                            L.tiles1z.push_back(make_int4(i, (int)(bx * P1Z_TX), (int)(by * P1Z_TX), 0));
+                            for (int64_t sx = 0; sx < S && (S * bx + sx) * TX < n; ++sx)
+                                L.tiles1z.push_back(make_int4(i, (int)((S * bx + sx) * TX), (int)(by * TY), 0));
             if (L.tiles1z.size() > (size_t)INT32_MAX) return PALD_ERR_UNSUPPORTED;
         }
         for (int32_t i : order) emit_p2(i);
@@ -599,8 +600,8 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
     const int64_t ntiles1 = (int64_t)plan->L.tiles1z.size();
         for (int64_t t0 = 0; t0 < ntiles1; t0 += kMaxGrid1) {
             const int64_t nt = std::min<int64_t>(kMaxGrid1, ntiles1 - t0);
-            batched_focus_kernel<<<(unsigned)nt, P1Z_NT, 0, s>>>(plan->d_tiles1z, (int32_t)ntiles1, plan->d_mats, D,
-                                                                  U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
+            batched_focus_kernel<<<(unsigned)nt, BatchFocusCfg::NT, 0, s>>>(
+                plan->d_tiles1z, (int32_t)ntiles1, plan->d_mats, D, U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
     batched_cohesion_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(

@@ -56,6 +56,12 @@ constexpr int64_t P1_TILES_PER_LAUNCH = 32768;
 constexpr int64_t P1Z_TILES_PER_LAUNCH = 1 << 20;  // n = 65536: 8 launches of about 1 s
 constexpr int64_t P2_TILES_PER_LAUNCH = 65536;
 constexpr int64_t TRI_TILES_PER_LAUNCH = 8192;
+// A dispatch counts its work-items along x in 32 bits: every launched piece
+// must stay below 2^32 of them.
+constexpr int64_t MAX_X_ITEMS = (int64_t)1 << 32;
+static_assert(P1_TILES_PER_LAUNCH * P1::NT < MAX_X_ITEMS && P1Z_TILES_PER_LAUNCH * P1Z_NT < MAX_X_ITEMS &&
+                  P2_TILES_PER_LAUNCH * P2::NT < MAX_X_ITEMS,
+              "launch pieces must hold fewer than 2^32 work-items");
 
 // ---- options -----------------------------------------------------------------
 struct Opts {
@@ -166,14 +172,18 @@ pald_status run_pass1(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_
         zero_i32_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(U, ldu, n);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
-    {
+    // (in pieces of at most per_launch tiles, as above: a dispatch holds fewer
+    // than 2^32 work-items along x)
+    const int64_t per_launch = P1_LANES_Z ? P1Z_TILES_PER_LAUNCH : P1_TILES_PER_LAUNCH;
+    for (int64_t t0 = 0; t0 < p.tiles1; t0 += per_launch) {
         ScopedTiming tm(timing, 0, s);
+        const unsigned g = (unsigned)std::min<int64_t>(per_launch, p.tiles1 - t0);
         if (P1_LANES_Z)
-            pass1z_focus_kernel<<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1Z_NT, 0, s>>>(
-                D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
+            pass1z_focus_kernel<<<dim3(g, (unsigned)p.z_chunks), P1Z_NT, 0, s>>>(D, n, ldd, U, ldu, nullptr, ldw,
+                                                                                p.z_per_chunk, 1, vec, (int32_t)t0);
         else
-            pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3((unsigned)p.tiles1, (unsigned)p.z_chunks), P1::NT, 0,
-                                                            s>>>(D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, 0);
+            pass1_focus_kernel<P1_T, P1_RX, P1_RY, P1_KZ><<<dim3(g, (unsigned)p.z_chunks), P1::NT, 0, s>>>(
+                D, n, ldd, U, ldu, nullptr, ldw, p.z_per_chunk, 1, vec, (int32_t)t0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     if (W) {
@@ -584,6 +594,7 @@ struct pald_batch_graph {
 namespace {
 
 constexpr int64_t kMaxGrid1 = (int64_t)1 << 22;  // pass-1 tiles per launch of the split mode
+static_assert(kMaxGrid1 * BatchFocusCfg::NT < MAX_X_ITEMS, "launch pieces must hold fewer than 2^32 work-items");
 
 pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *U, float *C, void *ws,
                           hipStream_t s) {

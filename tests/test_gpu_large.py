@@ -67,6 +67,17 @@ def test_config_aniso16d_n65536(capsys):
     assert abs(total - N / 2) <= 1e-6 * N / 2, f"sum(C) = {total!r}, expected {N / 2}"
     log(f"[large] invariants ok, sum(C) = {total:.6f}")
 
+    # pass 1 split over z: its tile grid (2^23 tiles of 512 threads, times the
+    # chunks) is launched in pieces; one dispatch would overflow the 32-bit
+    # work-item count along x and silently skip tiles
+    t0 = time.time()
+    U2 = pald.focus_sizes(D, z_chunks=2)
+    torch.cuda.synchronize()
+    assert torch.equal(U2, U), "pass 1 split over z differs from the unsplit pass 1"
+    del U2
+    torch.cuda.empty_cache()
+    log(f"[large] z-split pass 1 equal to the unsplit one ({time.time() - t0:.1f}s)")
+
     # oracle rows (the oracle needs all of D on the host)
     rows = np.sort(np.random.default_rng(5).choice(N, size=ORACLE_ROWS, replace=False))
     t0 = time.time()

@@ -67,16 +67,19 @@ def test_config_aniso16d_n65536(capsys):
     assert abs(total - N / 2) <= 1e-6 * N / 2, f"sum(C) = {total!r}, expected {N / 2}"
     log(f"[large] invariants ok, sum(C) = {total:.6f}")
 
-    # pass 1 split over z: its tile grid (2^23 tiles of 512 threads, times the
-    # chunks) is launched in pieces; one dispatch would overflow the 32-bit
-    # work-item count along x and silently skip tiles
-    t0 = time.time()
-    U2 = pald.focus_sizes(D, z_chunks=2)
-    torch.cuda.synchronize()
-    assert torch.equal(U2, U), "pass 1 split over z differs from the unsplit pass 1"
-    del U2
-    torch.cuda.empty_cache()
-    log(f"[large] z-split pass 1 equal to the unsplit one ({time.time() - t0:.1f}s)")
+    # At this size pass 1 runs split over z (4 chunks, atomic counts) by
+    # default; the unsplit pass 1 and a 2-chunk split must give the same U.
+    # Both tile grids (2^23 tiles of 512 threads) are launched in pieces: one
+    # dispatch would overflow the 32-bit work-item count along x and silently
+    # skip tiles.
+    for zc in (1, 2):
+        t0 = time.time()
+        U2 = pald.focus_sizes(D, z_chunks=zc)
+        torch.cuda.synchronize()
+        assert torch.equal(U2, U), f"pass 1 with z_chunks={zc} differs from the default split"
+        del U2
+        torch.cuda.empty_cache()
+        log(f"[large] pass 1 with z_chunks={zc} equal to the default ({time.time() - t0:.1f}s)")
 
     # oracle rows (the oracle needs all of D on the host)
     rows = np.sort(np.random.default_rng(5).choice(N, size=ORACLE_ROWS, replace=False))

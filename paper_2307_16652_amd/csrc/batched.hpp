@@ -152,7 +152,7 @@ __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const 
 
 // One tile per workgroup; launched in pieces of gridDim.x tiles from tile0.
 __global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void batched_focus_kernel(
-    const int4 *__restrict__ tiles, int32_t ntiles, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+    const int4 *__restrict__ tiles, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     int32_t *__restrict__ U, float *__restrict__ Wr, uint64_t *__restrict__ stamps, int32_t d_aligned,
     int32_t tile0) {
     __shared__ uint32_t smw[BatchFocusCfg::LDS_WORDS];

@@ -617,7 +617,7 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
         for (int64_t t0 = 0; t0 < ntiles1; t0 += kMaxGrid1) {
             const int64_t nt = std::min<int64_t>(kMaxGrid1, ntiles1 - t0);
             batched_focus_kernel<<<(unsigned)nt, BatchFocusCfg::NT, 0, s>>>(
-                plan->d_tiles1z, (int32_t)ntiles1, plan->d_mats, D, U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
+                plan->d_tiles1z, plan->d_mats, D, U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
     batched_cohesion_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(

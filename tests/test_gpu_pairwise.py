@@ -232,7 +232,8 @@ def test_config_uniform2d_n256_full():
     D = synth.uniform2d()
     U, C, err = parity(D, "uniform2d n=256 (full oracle)")
     check_invariants(U, C, "uniform2d")
-    log(f"  max rel err {err:.3e}")
+    _, _, err64 = parity(D, "uniform2d n=256 (full oracle), FP64 form", accum="f64")
+    log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
 
 
 def test_config_mixture8d_n4096_full():
@@ -246,7 +247,9 @@ def test_config_mixture8d_n4096_full():
     assert_u_equal(U, Uo, "mixture8d n=4096")
     err = assert_c_close(C, Co, what="mixture8d n=4096")
     check_invariants(U, C, "mixture8d")
-    log(f"  max rel err {err:.3e}")
+    _, C64 = gpu_cohesion(D, accum="f64")
+    err64 = assert_c_close(C64, Co, what="mixture8d n=4096, FP64 form")
+    log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
 
 
 def test_config_grid3d_n16384_sampled():
@@ -256,7 +259,8 @@ def test_config_grid3d_n16384_sampled():
     rows = np.concatenate([[0, 16383], rows])
     U, C, err = parity(D, "grid3d n=16384 (26 oracle rows)", rows=rows)
     check_invariants(U, C, "grid3d")
-    log(f"  max rel err {err:.3e}")
+    _, _, err64 = parity(D, "grid3d n=16384 (26 oracle rows), FP64 form", rows=rows, accum="f64")
+    log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
 
 
 def test_diagonal_identity_without_coincident_points():

@@ -160,6 +160,13 @@ __global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void b
     batched_focus_one((int)threadIdx.x, smw, tiles[k], mats, D, U, Wr, stamps, d_aligned);
 }
 
+// WITH_P1: the queue holds pass-1 items too (the one-launch form); without
+// them (split mode) the kernel carries the pass-2 path only, with its own
+// register allocation.  P2_FEW_SGPR picks the compare block's form.
+#ifndef PALD_BATCH_SPLIT_FEW_SGPR
+#define PALD_BATCH_SPLIT_FEW_SGPR 1
+#endif
+template <bool WITH_P1, bool P2_FEW_SGPR>
 __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_cohesion_kernel(
     const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     int32_t *__restrict__ U, float *__restrict__ C, float *__restrict__ Wr, double *__restrict__ Pr,
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                 atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
             const int64_t n = uniform_i32(s_m.n);
             const bool vec_d = d_aligned && uniform_i32(s_m.vec_d);
-            if (kind == ITEM_PASS1) {
+            if (WITH_P1 && kind == ITEM_PASS1) {
                 int32_t bx, by;
                 tri_tile(tile, bx, by);
                 int32_t *Um = U ? U + moff : nullptr;
@@ -242,10 +249,10 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                     out.tile = Pr + mpoff + ((int64_t)tile * mychunks + chunk) * TT2;
                 }
                 if (t2 == BATCH_P2_T)
-                    pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, true>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff,
+                    pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, P2_FEW_SGPR>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff,
                                                                            mldw, out, bx, bz, ybeg, yend, vec_d, true);
                 else
-                    pass2_tile<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY, false, true>(opaque_tid(), sm, D + moff, n, n,
+                    pass2_tile<BATCH_P2S_T, BATCH_P2S_RX, BATCH_P2_KY, false, P2_FEW_SGPR>(opaque_tid(), sm, D + moff, n, n,
                                                                              Wr + mwoff, mldw, out, bx, bz, ybeg, yend,
                                                                              vec_d, true);
                 if (mychunks > 1) {

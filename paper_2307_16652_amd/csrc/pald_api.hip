@@ -570,7 +570,7 @@ int32_t device_cus(int dev) {
 
 int32_t resident_per_cu() {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cohesion_kernel, BATCH_THREADS, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_cohesion_kernel<true, true>, BATCH_THREADS, 0) !=
             hipSuccess ||
         per < 1)
         per = 1;
@@ -620,7 +620,9 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
                 plan->d_tiles1z, plan->d_mats, D, U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
-    batched_cohesion_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
+    auto kern = plan->L.tiles1z.empty() ? batched_cohesion_kernel<true, true>
+                                        : batched_cohesion_kernel<false, (bool)PALD_BATCH_SPLIT_FEW_SGPR>;
+    kern<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
         plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, U, C, Wr, Pr, ctr, plan->count, stamps,
         aligned16(D) ? 1 : 0);
     return launch_status();

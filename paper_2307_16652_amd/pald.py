@@ -532,8 +532,16 @@ class BatchGraph:
             pass
 
 
-def cohesion_batched(mats, config: BatchConfig | None = None):
-    """[(U_i, C_i)] for a list of square float32 cuda matrices, in one batched launch."""
+def cohesion_batched(mats, config: BatchConfig | None | str = "tuned"):
+    """[(U_i, C_i)] for a list of square float32 cuda matrices, in one batched run.
+
+    config: a BatchConfig, None for the library's built-in defaults (the
+    one-launch form), or "tuned" (default) for the autotuned table of this GPU
+    (tuning/batch_gfx950.json), if one was written."""
+    if isinstance(config, str):
+        if config != "tuned":
+            raise ValueError('config must be a BatchConfig, None or "tuned"')
+        config = load_tuning()
     plan = BatchPlan([m.shape[0] for m in mats], config=config)
     try:
         Dp = plan.pack(mats)

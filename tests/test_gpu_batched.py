@@ -261,6 +261,24 @@ def test_split_pass1_graph_timestamps_unaligned_no_u():
     assert torch.equal(C0, C1)
 
 
+def test_cohesion_batched_convenience():
+    """pald.cohesion_batched with the tuned table (default) and with the library
+    defaults: oracle parity and the same results from both."""
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    mats = make_batch([70, 3, 129, 40], seed=16)
+    tuned = pald.cohesion_batched([torch.from_numpy(m).cuda() for m in mats])
+    plain = pald.cohesion_batched([torch.from_numpy(m).cuda() for m in mats], config=None)
+    torch.cuda.synchronize()
+    Us = [u.cpu().numpy() for u, _ in tuned]
+    Cs = [c.cpu().numpy() for _, c in tuned]
+    check_all(mats, Us, Cs, what="cohesion_batched")
+    for (u1, c1), (u2, c2) in zip(tuned, plain):
+        assert torch.equal(u1, u2) and torch.equal(c1, c2)
+
+
 def test_config_batch_2000_sampled():
     """The 2000-matrix workload (n uniform in [32, 1024], 2-5 clusters in R^4):
     oracle on every 20th matrix, invariants on all."""

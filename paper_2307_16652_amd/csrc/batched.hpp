@@ -168,6 +168,47 @@ __global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void b
 #ifndef PALD_BATCH_SPLIT_FEW_SGPR
 #define PALD_BATCH_SPLIT_FEW_SGPR 1
 #endif
+// Split mode, second launch when every matrix runs 64-wide pass-2 tiles with
+// no y split (the tuned table's choice): a lean persistent kernel holding
+// only what that needs across a tile.  Workgroups take the pass-2 items
+// (largest matrix first) with one atomic increment of ctr[0] (zeroed by the
+// reset kernel).  With less state live across the tile its loop reloads
+// fewer spilled scalars than the general kernel's: 106.5 against 116.8 ms per
+// 2000-matrix batch (107.5 with the scalar-register-saving compare block).
+#ifndef PALD_BATCH_LEAN_PASS2
+#define PALD_BATCH_LEAN_PASS2 1
+#endif
+#ifndef PALD_BATCH_LEAN_FEW_SGPR
+#define PALD_BATCH_LEAN_FEW_SGPR 0
+#endif
+__global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_pass2_lean_kernel(
+    const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+    float *__restrict__ C, const float *__restrict__ Wr, uint32_t *__restrict__ ctr, uint64_t *__restrict__ stamps,
+    int32_t d_aligned) {
+    __shared__ uint4 sm[BatchP2::LDS_VEC];
+    __shared__ int32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int32_t it = uniform_i32(s_item);
+        if (it >= total) break;
+        const int4 item = items[it];
+        const int32_t mi = item.x;
+        const int64_t moff = mats[mi].off, mwoff = mats[mi].woff, n = mats[mi].n, ldw = mats[mi].ldw;
+        const bool vec_d = d_aligned && mats[mi].vec_d;
+        int32_t bx, bz;
+        tri_tile(item.z, bx, bz);
+        pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw,
+                                                               Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0, n,
+                                                               vec_d, true);
+        if (stamps && threadIdx.x == 0) {
+            __threadfence();
+            atomicMax((unsigned long long *)&stamps[2 * mi + 1], (unsigned long long)wall_clock64());
+        }
+        __syncthreads();  // s_item and the tile buffers are reused by the next item
+    }
+}
+
 template <bool WITH_P1, bool P2_FEW_SGPR>
 __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_cohesion_kernel(
     const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,

@@ -588,6 +588,7 @@ struct pald_batch_plan {
     BatchMatrix *d_mats = nullptr;
     int4 *d_items = nullptr;
     int4 *d_tiles1z = nullptr;
+    bool lean2 = false;  // split mode, every matrix 64-wide pass-2 tiles, no y split
     size_t off_w = 0, off_p = 0, off_ctr = 0, off_stamps = 0, ws_bytes = 0;
 };
 
@@ -620,6 +621,11 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
                 plan->d_tiles1z, plan->d_mats, D, U, Wr, stamps, aligned16(D) ? 1 : 0, (int32_t)t0);
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
+    if (plan->lean2) {
+        batched_pass2_lean_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
+            plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, C, Wr, ctr, stamps, aligned16(D) ? 1 : 0);
+        return launch_status();
+    }
     auto kern = plan->L.tiles1z.empty() ? batched_cohesion_kernel<true, true>
                                         : batched_cohesion_kernel<false, (bool)PALD_BATCH_SPLIT_FEW_SGPR>;
     kern<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
@@ -653,6 +659,8 @@ pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const p
         delete p;
         return st;
     }
+    p->lean2 = PALD_BATCH_LEAN_PASS2 && !p->L.tiles1z.empty();
+    for (const BatchMatrix &m : p->L.mats) p->lean2 = p->lean2 && m.y_chunks == 1 && m.tile2 == BATCH_P2_T;
     size_t off = 0;
     p->off_w = off;
     off = align_up(off + (size_t)p->L.w_floats * sizeof(float), ALIGN);

@@ -223,15 +223,17 @@ def test_split_pass1(tile, chunks):
         assert np.array_equal(Cs[i].view(np.int32), Cf[i].view(np.int32)), f"matrix {i}: C differs"
 
 
-def test_split_pass1_graph_timestamps_unaligned_no_u():
+@pytest.mark.parametrize("buckets", [[(100, 1), (1 << 30, 2)], [(1 << 30, 1, 64)]], ids=["general", "lean"])
+def test_split_pass1_graph_timestamps_unaligned_no_u(buckets):
     """Split mode: graph replays with eager work between them, timestamps, a packed
-    base 4 bytes past an aligned address, and no U output."""
+    base 4 bytes past an aligned address, and no U output; with a y split (the
+    general persistent pass-2 kernel) and without (the lean one)."""
     import torch
 
     from paper_2307_16652_amd import pald
 
     mats = make_batch([77, 150, 3, 64, 201, 36], seed=15)
-    cfg = pald.make_batch_config([(100, 1), (1 << 30, 2)], timestamps=True, split_pass1=True)
+    cfg = pald.make_batch_config(buckets, timestamps=True, split_pass1=True)
     plan = pald.BatchPlan([m.shape[0] for m in mats], config=cfg)
     flat = np.concatenate([m.reshape(-1) for m in mats])
     buf = torch.zeros(flat.size + 1, dtype=torch.float32, device="cuda")

@@ -198,9 +198,9 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
         const bool vec_d = d_aligned && mats[mi].vec_d;
         int32_t bx, bz;
         tri_tile(item.z, bx, bz);
-        pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR>(opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw,
-                                                               Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0, n,
-                                                               vec_d, true);
+        pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR>(
+            opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw, Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0, n,
+            vec_d, true);
         if (stamps && threadIdx.x == 0) {
             __threadfence();
             atomicMax((unsigned long long *)&stamps[2 * mi + 1], (unsigned long long)wall_clock64());

@@ -117,9 +117,9 @@ def batched_bench(dev, reps: int = 3, one_launch_form: bool = True):
     ns = synth.batch_sizes()
     progress(f"batched: generating {len(ns)} matrices")
     mats = [synth.pairwise_distances(synth.batch_points(i, int(n))) for i, n in enumerate(ns)]
-    cfg = pald.load_tuning() if hasattr(pald, "load_tuning") else None
-    plan = pald.BatchPlan([int(n) for n in ns], config=cfg)
-    plan_split = bool(cfg is not None and cfg.flags & pald.BATCH_SPLIT_PASS1)
+    # the library's built-in configuration (the autotuner's table compiled into it)
+    plan = pald.BatchPlan([int(n) for n in ns], config=None)
+    plan_split = bool((pald.batch_queue([int(ns[0])], plan.grid)[1] == 0).all())
     Dp = torch.from_numpy(np.concatenate([m.reshape(-1) for m in mats])).to(dev)
     del mats
     ws = plan.workspace(dev)
@@ -138,12 +138,10 @@ def batched_bench(dev, reps: int = 3, one_launch_form: bool = True):
     batch_ms = ev0.elapsed_time(ev1) / reps
     g.close()
 
-    def timestamped(flags_off=0):
-        """Per-matrix (start, end) device times of one run of the tuned config (minus flags_off)."""
-        tcfg = pald.load_tuning(timestamps=True)
-        if tcfg is None:
-            tcfg = pald.make_batch_config(timestamps=True)
-        tcfg.flags &= ~flags_off
+    def timestamped(one_launch: bool = False):
+        """Per-matrix (start, end) device times of one run of the built-in config
+        (in the one-launch form if asked)."""
+        tcfg = pald.make_batch_config(timestamps=True, split_pass1=False if one_launch else None)
         tplan = pald.BatchPlan([int(n) for n in ns], config=tcfg)
         tws = tplan.workspace(dev)
         tplan.run(Dp, Up, Cp, tws)
@@ -161,8 +159,7 @@ def batched_bench(dev, reps: int = 3, one_launch_form: bool = True):
     # matrix's pass 1 in the first launch
     fused = None
     if plan_split and one_launch_form:
-        fcfg = pald.load_tuning()
-        fcfg.flags &= ~pald.BATCH_SPLIT_PASS1
+        fcfg = pald.make_batch_config(split_pass1=False)
         fplan = pald.BatchPlan([int(n) for n in ns], config=fcfg)
         fws = fplan.workspace(dev)
         fplan.run(Dp, Up, Cp, fws)
@@ -178,7 +175,7 @@ def batched_bench(dev, reps: int = 3, one_launch_form: bool = True):
         fg.close()
         fplan.close()
         del fws
-        fst, fen = timestamped(pald.BATCH_SPLIT_PASS1)
+        fst, fen = timestamped(one_launch=True)
         flat_ = fen - fst
         fused = {"ms_per_batch": round(fms, 3), "matrices_per_s": round(len(ns) / (fms / 1e3), 1),
                  "latency_us_p50": round(float(np.percentile(flat_, 50)), 1),

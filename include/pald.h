@@ -63,7 +63,10 @@ typedef enum pald_status {
 
 /* Algorithm used for the two passes. */
 enum {
-    PALD_VARIANT_AUTO = 0,     /* library choice (currently pairwise) */
+    PALD_VARIANT_AUTO = 0,     /* the built-in tuned choice for n (autotuner
+                                  table compiled into the library: pairwise at
+                                  every tuned size on gfx950); pairwise where
+                                  the choice does not take the other options */
     PALD_VARIANT_PAIRWISE = 1, /* Section 3 pairwise algorithm: output-stationary
                                   (x,y) tiles for U, (x,z) tiles for C */
     PALD_VARIANT_TRIPLET = 2,  /* Section 3 triplet algorithm: one visit per
@@ -268,11 +271,19 @@ typedef struct pald_batch_bucket {
  * Without it, pass-1 items (64 x 64 lanes-over-pairs tiles) share the queue
  * and the persistent kernel's register budget with the pass-2 items. */
 #define PALD_BATCH_SPLIT_PASS1 2u
+/* The one-launch form: pass-1 and pass-2 items share the persistent queue. */
+#define PALD_BATCH_ONE_LAUNCH 4u
 
+/* Built-in configuration: the autotuner's table for MI355X, compiled into the
+ * library from its records (buckets, grid, queue lag and launch form; on
+ * gfx950 the split form with 64-wide pass-2 tiles and no y split).  A NULL
+ * config means all of it; in a config, every field left 0 takes its built-in
+ * value, and the launch form is the built-in one unless exactly one of
+ * PALD_BATCH_SPLIT_PASS1 / PALD_BATCH_ONE_LAUNCH is set. */
 typedef struct pald_batch_config {
     int32_t nbuckets;          /* entries used in bucket[]; 0 = the built-in tuned table */
-    int32_t workgroups_per_cu; /* persistent grid = CUs x this; 0 = resident capacity */
-    int32_t queue_lag;         /* in units of the grid size; 0 = default (2) */
+    int32_t workgroups_per_cu; /* persistent grid = CUs x this; 0 = built-in (resident capacity) */
+    int32_t queue_lag;         /* in units of the grid size; 0 = built-in (2) */
     uint32_t flags;            /* PALD_BATCH_* */
     pald_batch_bucket bucket[PALD_BATCH_MAX_BUCKETS];
 } pald_batch_config;
@@ -280,9 +291,11 @@ typedef struct pald_batch_config {
 /*
  * Builds the plan for `count` matrices of sizes n_host[0..count) (host array,
  * every n_i >= 2) on the current device: chooses tiles and y-splits per size
- * (cfg NULL = defaults), builds the queue and uploads it and the per-matrix
- * table.  Synchronous; the only allocating call of the batched mode.
- * Errors: PALD_ERR_ARG (count < 1, null pointers, n_i < 2, bad config),
+ * (cfg NULL = the built-in tuned configuration), builds the queue and uploads
+ * it and the per-matrix table.  Synchronous; the only allocating call of the
+ * batched mode.
+ * Errors: PALD_ERR_ARG (count < 1, null pointers, n_i < 2, bad config, both
+ * launch-form flags),
  * PALD_ERR_NOMEM, PALD_ERR_DEVICE.
  */
 pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host,

@@ -2,7 +2,9 @@
 
     python -m paper_2307_16652_amd.build          # or build() from Python
 
-hipcc cross-compiles for gfx950 without a GPU present.
+hipcc cross-compiles for gfx950 without a GPU present.  Every build first
+regenerates csrc/tuned_gfx950.h, the built-in tuned tables, from the
+autotuner's records in tuning/.
 """
 from __future__ import annotations
 
@@ -43,8 +45,87 @@ def sources():
     return [os.path.join(CSRC, f) for f in ("pald_api.hip", "frontend_api.hip")]
 
 
+TUNING = os.path.join(PKG, "tuning")
+TUNED_HEADER = os.path.join(CSRC, "tuned_gfx950.h")
+_VARIANT_ENUM = {"pairwise": "PALD_VARIANT_PAIRWISE", "triplet": "PALD_VARIANT_TRIPLET",
+                 "hybrid": "PALD_VARIANT_HYBRID"}
+
+
+def tuned_header_text() -> str:
+    """C++ text of the library's built-in tuned tables, from the autotuner's JSON
+    records in tuning/ (batch_gfx950.json: batched buckets, grid, queue lag and
+    launch form; variants_gfx950.json: single-matrix variant per size).  A
+    missing record gives the untuned defaults."""
+    import json
+
+    buckets, wpc, lag, split, src = [{"n_max": 1 << 30, "tile": 64, "y_chunks": 1}], 0, 0, False, []
+    path = os.path.join(TUNING, "batch_gfx950.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            rec = json.load(f)
+        buckets = rec["buckets"]
+        wpc, lag, split = int(rec.get("workgroups_per_cu", 0)), int(rec.get("queue_lag", 0)), \
+            bool(rec.get("split_pass1", False))
+        src.append("tuning/batch_gfx950.json")
+    variants = [(2, "pairwise")]
+    path = os.path.join(TUNING, "variants_gfx950.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            variants = sorted((int(r["n"]), str(r["best"])) for r in json.load(f)["sizes"])
+        src.append("tuning/variants_gfx950.json")
+    if not 1 <= len(buckets) <= 8:
+        raise ValueError("the batched tuning record needs 1 to 8 buckets")
+    bl = ",\n    ".join(f"{{{int(b['n_max'])}, {int(b.get('tile', 64))}, {int(b.get('y_chunks', 1))}, 0}}"
+                         for b in buckets)
+    vl = ",\n    ".join(f"{{{n}, {_VARIANT_ENUM[v]}}}" for n, v in variants)
+    return f"""// tuned_gfx950.h -- the library's built-in tuned tables for MI355X (gfx950).
+// Written by build.py on every build from the autotuner's records
+// ({', '.join(src) or 'none found: untuned defaults'}); do not edit by hand:
+// rerun paper_2307_16652_amd.tune, then the build.
+#pragma once
+
+#include <stdint.h>
+
+#include "pald.h"
+
+namespace pald_tuned {{
+
+// batched mode: per-size buckets (n_max ascending), persistent grid per CU
+// (0 = resident capacity), queue lag (0 = default) and launch form
+constexpr pald_batch_bucket kBatchBuckets[] = {{
+    {bl}}};
+constexpr int32_t kBatchWorkgroupsPerCu = {wpc};
+constexpr int32_t kBatchQueueLag = {lag};
+constexpr bool kBatchSplitPass1 = {'true' if split else 'false'};
+
+// single-matrix variant for PALD_VARIANT_AUTO: the entry with the largest n
+// not above the problem's n (the first entry below that)
+struct VariantPick {{
+    int64_t n;
+    int32_t variant;
+}};
+constexpr VariantPick kVariants[] = {{
+    {vl}}};
+
+}}  // namespace pald_tuned
+"""
+
+
+def write_tuned_header() -> str:
+    text = tuned_header_text()
+    old = None
+    if os.path.exists(TUNED_HEADER):
+        with open(TUNED_HEADER) as f:
+            old = f.read()
+    if old != text:
+        with open(TUNED_HEADER, "w") as f:
+            f.write(text)
+    return TUNED_HEADER
+
+
 def build(verbose: bool = False) -> str:
     """Compile libpald.so for gfx950; always recompiles."""
+    write_tuned_header()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, *sources()]
     if verbose:

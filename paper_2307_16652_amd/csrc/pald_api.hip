@@ -16,6 +16,7 @@
 #include "pairwise.hpp"
 #include "batched.hpp"
 #include "triplet.hpp"
+#include "tuned_gfx950.h"
 
 namespace {
 
@@ -87,6 +88,20 @@ pald_status read_opts(const pald_options *o, Opts &out) {
     out.z_chunks = o->z_chunks;
     out.flags = o->flags;
     return PALD_OK;
+}
+
+// PALD_VARIANT_AUTO -> the tuned variant for n, unless it cannot take the
+// other options (the triplet variant: compensated accumulation without
+// splits; the hybrid: no z split), in which case pairwise.
+void resolve_variant(int64_t n, Opts &o) {
+    if (o.variant != PALD_VARIANT_AUTO) return;
+    int32_t v = pald_tuned::kVariants[0].variant;
+    for (const auto &e : pald_tuned::kVariants)
+        if (e.n <= n) v = e.variant;
+    if (v == PALD_VARIANT_TRIPLET && (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0))
+        v = PALD_VARIANT_PAIRWISE;
+    if (v == PALD_VARIANT_HYBRID && o.z_chunks != 0) v = PALD_VARIANT_PAIRWISE;
+    o.variant = v;
 }
 
 // ---- launch planning ------------------------------------------------------
@@ -301,6 +316,32 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     return launch_status();
 }
 
+// Both passes of the pairwise or hybrid variant with plan p in the workspace
+// at `base` (at least p.bytes, 256-byte aligned); arguments already checked.
+pald_status run_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
+                         char *base, const Plan &p, const Opts &o, hipStream_t s) {
+    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
+    float *W = reinterpret_cast<float *>(base + p.off_w);
+    int32_t *Ub = U;
+    int64_t ldub = ldu;
+    if (!Ub && p.need_u_scratch) {
+        Ub = reinterpret_cast<int32_t *>(base + p.off_u);
+        ldub = n;
+    }
+    if (o.variant == PALD_VARIANT_HYBRID) {
+        // triplet pass 1 (one visit per unordered triple, integer atomics), then W
+        if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
+        ScopedTiming tm(timing, 1, s);
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, p.ldw, n);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    } else if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, p.ldw, p, s, timing); st != PALD_OK) {
+        return st;
+    }
+    double *part = p.y_chunks > 1 ? reinterpret_cast<double *>(base + p.off_part) : nullptr;
+    return run_pass2(D, n, ldd, W, p.ldw, C, ldc, part, p, o.accum == PALD_ACC_F64, s, timing);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -323,6 +364,7 @@ int32_t pald_version(void) { return 10000 * 0 + 100 * 1 + 0; }
 size_t pald_workspace_bytes(int64_t n, const pald_options *opt) {
     Opts o;
     if (n < 2 || read_opts(opt, o) != PALD_OK) return 0;
+    resolve_variant(n, o);
     if (o.variant == PALD_VARIANT_TRIPLET) return triplet_workspace_bytes(n);
     Plan p;
     if (make_plan(n, o, p) != PALD_OK) return 0;
@@ -334,6 +376,7 @@ pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd, int32_t *U,
     Opts o;
     if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
     if (!D || !U || n < 2 || ldd < n || ldu < n) return PALD_ERR_ARG;
+    resolve_variant(n, o);
     if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID)
         return triplet_focus(D, n, ldd, U, ldu, (hipStream_t)stream, (o.flags & PALD_FLAG_TIMING) != 0);
     Plan p;
@@ -347,6 +390,7 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
     if (!D || !C || !ws || n < 2 || ldd < n || ldc < n || (U && ldu < n)) return PALD_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
+    resolve_variant(n, o);
     hipStream_t s = (hipStream_t)stream;
     const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
     if (o.variant == PALD_VARIANT_TRIPLET) {
@@ -357,26 +401,7 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
     if (ws_bytes < p.bytes) return PALD_ERR_ARG;
-    char *base = static_cast<char *>(ws);
-    float *W = reinterpret_cast<float *>(base + p.off_w);
-    int32_t *Ub = U;
-    int64_t ldub = ldu;
-    if (!Ub && p.need_u_scratch) {
-        Ub = reinterpret_cast<int32_t *>(base + p.off_u);
-        ldub = n;
-    }
-    if (o.variant == PALD_VARIANT_HYBRID) {
-        // triplet pass 1 (one visit per unordered triple, integer atomics), then W
-        if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
-        ScopedTiming tm(timing, 1, s);
-        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
-        weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, p.ldw, n);
-        if (pald_status st = launch_status(); st != PALD_OK) return st;
-    } else if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, p.ldw, p, s, timing); st != PALD_OK) {
-        return st;
-    }
-    double *part = p.y_chunks > 1 ? reinterpret_cast<double *>(base + p.off_part) : nullptr;
-    return run_pass2(D, n, ldd, W, p.ldw, C, ldc, part, p, o.accum == PALD_ACC_F64, s, timing);
+    return run_cohesion(D, n, ldd, U, ldu, C, ldc, static_cast<char *>(ws), p, o, s);
 }
 
 pald_status pald_check_input(const float *D, int64_t n, int64_t ldd, void *ws, size_t ws_bytes, void *stream,
@@ -426,12 +451,18 @@ int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds) {
 
 namespace {
 
-// Built-in bucket table (from the autotuner on MI355X; see tune.py).
-const pald_batch_bucket kDefaultBuckets[] = {
-    {1 << 30, 64, 1, 0},
-};
-constexpr int kDefaultNumBuckets = (int)(sizeof(kDefaultBuckets) / sizeof(kDefaultBuckets[0]));
-constexpr int kDefaultLag = 2;
+// Built-in configuration: the autotuner's table for MI355X (tuned_gfx950.h).
+constexpr const pald_batch_bucket *kDefaultBuckets = pald_tuned::kBatchBuckets;
+constexpr int kDefaultNumBuckets = (int)(sizeof(pald_tuned::kBatchBuckets) / sizeof(pald_tuned::kBatchBuckets[0]));
+static_assert(kDefaultNumBuckets >= 1 && kDefaultNumBuckets <= PALD_BATCH_MAX_BUCKETS, "tuned bucket table size");
+constexpr int kDefaultLag = pald_tuned::kBatchQueueLag > 0 ? pald_tuned::kBatchQueueLag : 2;
+
+// Launch form: the caller's flag if it sets one, else the tuned choice.
+bool batch_split(const pald_batch_config *cfg) {
+    if (cfg && (cfg->flags & PALD_BATCH_SPLIT_PASS1)) return true;
+    if (cfg && (cfg->flags & PALD_BATCH_ONE_LAUNCH)) return false;
+    return pald_tuned::kBatchSplitPass1;
+}
 
 struct BatchLayout {
     std::vector<BatchMatrix> mats;
@@ -447,7 +478,8 @@ struct BatchLayout {
 pald_status check_config(const pald_batch_config *cfg) {
     if (!cfg) return PALD_OK;
     if (cfg->nbuckets < 0 || cfg->nbuckets > PALD_BATCH_MAX_BUCKETS || cfg->workgroups_per_cu < 0 ||
-        cfg->queue_lag < 0 || (cfg->flags & ~(PALD_BATCH_TIMESTAMPS | PALD_BATCH_SPLIT_PASS1)))
+        cfg->queue_lag < 0 || (cfg->flags & ~(PALD_BATCH_TIMESTAMPS | PALD_BATCH_SPLIT_PASS1 | PALD_BATCH_ONE_LAUNCH)) ||
+        ((cfg->flags & PALD_BATCH_SPLIT_PASS1) && (cfg->flags & PALD_BATCH_ONE_LAUNCH)))
         return PALD_ERR_ARG;
     for (int b = 0; b < cfg->nbuckets; ++b) {
         const pald_batch_bucket &k = cfg->bucket[b];
@@ -477,7 +509,7 @@ pald_status build_batch(int32_t count, const int64_t *n_host, const pald_batch_c
     if (count < 1 || !n_host || grid < 1) return PALD_ERR_ARG;
     if (pald_status st = check_config(cfg); st != PALD_OK) return st;
     L = BatchLayout{};
-    const bool split = cfg && (cfg->flags & PALD_BATCH_SPLIT_PASS1);
+    const bool split = batch_split(cfg);
     L.mats.resize(count);
     L.n.assign(n_host, n_host + count);
     L.off.resize(count);
@@ -647,7 +679,9 @@ pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const p
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PALD_ERR_DEVICE;
     const int32_t cus = device_cus(dev);
-    const int32_t per_cu = (cfg && cfg->workgroups_per_cu > 0) ? cfg->workgroups_per_cu : resident_per_cu();
+    const int32_t per_cu = (cfg && cfg->workgroups_per_cu > 0)         ? cfg->workgroups_per_cu
+                           : pald_tuned::kBatchWorkgroupsPerCu > 0 ? pald_tuned::kBatchWorkgroupsPerCu
+                                                                   : resident_per_cu();
     const int32_t grid = cus * per_cu;
     pald_batch_plan *p = new (std::nothrow) pald_batch_plan();
     if (!p) return PALD_ERR_NOMEM;

@@ -41,6 +41,7 @@ EXPORTED = (
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
 BATCH_SPLIT_PASS1 = 2
+BATCH_ONE_LAUNCH = 4
 
 
 class PaldError(RuntimeError):
@@ -72,10 +73,12 @@ class BatchConfig(ctypes.Structure):
 
 
 def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int = 0,
-                      timestamps: bool = False, split_pass1: bool = False) -> BatchConfig:
+                      timestamps: bool = False, split_pass1: bool | None = False) -> BatchConfig:
     """buckets: list of (n_max, y_chunks) or (n_max, y_chunks, tile) tuples, or dicts with keys
-    n_max / y_chunks / tile (tile = pass-2 tile side, 64 or 32; default 64).  split_pass1:
-    pass 1 of every matrix as a launch of its own before the persistent kernel."""
+    n_max / y_chunks / tile (tile = pass-2 tile side, 64 or 32; default 64); empty = the
+    library's built-in tuned buckets.  split_pass1: True = pass 1 of every matrix as a launch
+    of its own before the persistent kernel, False = the one-launch form, None = the
+    library's built-in tuned choice."""
     c = BatchConfig()
     buckets = list(buckets or [])
     if len(buckets) > BATCH_MAX_BUCKETS:
@@ -92,7 +95,8 @@ def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int =
     c.nbuckets = len(buckets)
     c.workgroups_per_cu = int(workgroups_per_cu)
     c.queue_lag = int(queue_lag)
-    c.flags = (BATCH_TIMESTAMPS if timestamps else 0) | (BATCH_SPLIT_PASS1 if split_pass1 else 0)
+    form = 0 if split_pass1 is None else (BATCH_SPLIT_PASS1 if split_pass1 else BATCH_ONE_LAUNCH)
+    c.flags = (BATCH_TIMESTAMPS if timestamps else 0) | form
     return c
 
 
@@ -100,27 +104,9 @@ def make_batch_config(buckets=None, workgroups_per_cu: int = 0, queue_lag: int =
 TUNING_PATH = os.path.join(PKG, "tuning", "batch_gfx950.json")
 
 
+#: per-size variant choice written by paper_2307_16652_amd.tune --variants; build.py
+#: compiles it into the library, whose PALD_VARIANT_AUTO follows it
 VARIANT_TUNING_PATH = os.path.join(PKG, "tuning", "variants_gfx950.json")
-_variant_table = None
-
-
-def choose_variant(n: int) -> str:
-    """The variant measured fastest (tuning/variants_gfx950.json) at the largest
-    tuned size <= n (the smallest tuned size below that); "pairwise" if untuned."""
-    global _variant_table
-    if _variant_table is None:
-        try:
-            with open(VARIANT_TUNING_PATH) as f:
-                _variant_table = sorted((int(r["n"]), str(r["best"])) for r in json.load(f)["sizes"])
-        except (OSError, ValueError, KeyError):
-            _variant_table = []
-    if not _variant_table:
-        return "pairwise"
-    best = _variant_table[0][1]
-    for size, v in _variant_table:
-        if size <= n:
-            best = v
-    return best if best in VARIANTS else "pairwise"
 
 
 def load_tuning(path: str | None = None, timestamps: bool = False) -> BatchConfig | None:
@@ -287,8 +273,6 @@ def cohesion(D, *, variant: str = "auto", accum: str = "compensated", y_chunks: 
     """(U, C): focus sizes (int32, or None if want_u is False) and cohesion (float32)."""
     torch = _torch()
     n, ldd = _check_matrix(D)
-    if variant == "auto" and accum == "compensated" and z_chunks == 0:
-        variant = choose_variant(n)
     opts = dict(variant=variant, accum=accum, y_chunks=y_chunks, z_chunks=z_chunks, timing=timing)
     o = make_options(**opts)
     if ws is None:
@@ -535,9 +519,10 @@ class BatchGraph:
 def cohesion_batched(mats, config: BatchConfig | None | str = "tuned"):
     """[(U_i, C_i)] for a list of square float32 cuda matrices, in one batched run.
 
-    config: a BatchConfig, None for the library's built-in defaults (the
-    one-launch form), or "tuned" (default) for the autotuned table of this GPU
-    (tuning/batch_gfx950.json), if one was written."""
+    config: a BatchConfig, None for the library's built-in configuration (the
+    autotuned table compiled into it), or "tuned" (default) for the autotuner's
+    record tuning/batch_gfx950.json read at run time (the same table unless the
+    record changed after the build)."""
     if isinstance(config, str):
         if config != "tuned":
             raise ValueError('config must be a BatchConfig, None or "tuned"')

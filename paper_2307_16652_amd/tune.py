@@ -19,14 +19,17 @@ clusters in R^4), for
 
 by coordinate descent on the measured time of one whole batched launch
 (median of `reps` graph replays), and writes the winner to
-tuning/batch_gfx950.json, which `pald.load_tuning()` (and so `bench.py`)
-picks up.  Both tile shapes are compiled into the batched kernel; the search
-picks one per bucket.
+tuning/batch_gfx950.json.  The next build (paper_2307_16652_amd.build)
+compiles that record into the library as its built-in batched configuration
+(what a NULL config gets), and `pald.load_tuning()` reads it at run time.
+Both tile shapes are compiled into the batched kernel; the search picks one
+per bucket.
 
 With --variants it instead times the pairwise, hybrid (triplet pass 1 +
 pairwise pass 2) and triplet variants of the single-matrix path on Gaussian
 mixtures of several sizes and writes, per size, the fastest one to
-tuning/variants_gfx950.json, which `pald.cohesion(variant="auto")` follows.
+tuning/variants_gfx950.json, which the next build compiles into the library's
+PALD_VARIANT_AUTO choice.
 """
 from __future__ import annotations
 

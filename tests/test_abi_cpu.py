@@ -45,6 +45,24 @@ def test_workspace_sizes():
     assert pald.workspace_bytes(1000, y_chunks=4) >= 4 * 1000 * 1000 * 8
 
 
+def test_auto_variant_follows_the_tuned_table():
+    """PALD_VARIANT_AUTO sizes its workspace for the variant the autotuner's record
+    (compiled into the library) picks at each n."""
+    import json
+
+    with open(pald.VARIANT_TUNING_PATH) as f:
+        table = sorted((int(r["n"]), r["best"]) for r in json.load(f)["sizes"])
+    for n in (100, 256, 300, 1024, 5000, 20000):
+        pick = table[0][1]
+        for size, v in table:
+            if size <= n:
+                pick = v
+        assert pald.workspace_bytes(n, variant="auto") == pald.workspace_bytes(n, variant=pick), n
+    # the triplet variant takes no forced split: AUTO with one runs pairwise
+    assert pald.workspace_bytes(3000, variant="auto", y_chunks=2) == \
+        pald.workspace_bytes(3000, variant="pairwise", y_chunks=2)
+
+
 def _opts(**kw):
     return ctypes.byref(pald.make_options(**kw))
 

@@ -75,7 +75,7 @@ SIZE_MIXES = {
 @pytest.mark.parametrize("grid", [1, 3, 64, 512])
 def test_queue_structure(mix, grid):
     sizes = SIZE_MIXES[mix]
-    items, tiles1 = pald.batch_queue(sizes, grid)
+    items, tiles1 = pald.batch_queue(sizes, grid, config=pald.make_batch_config(split_pass1=False))
     for m, n in enumerate(sizes):
         nb1 = -(-n // 64)
         assert tiles1[m] == nb1 * (nb1 + 1) // 2
@@ -106,7 +106,7 @@ def test_protocol_terminates(mix, workers):
 
 def test_model_detects_a_bad_queue():
     """Control: moving a pass-2 item ahead of its matrix's pass 1 deadlocks one worker."""
-    items, tiles1 = pald.batch_queue([70, 40], grid=1)
+    items, tiles1 = pald.batch_queue([70, 40], grid=1, config=pald.make_batch_config(split_pass1=False))
     bad = items.copy()
     k = int(np.where((bad[:, 1] == 1) & (bad[:, 0] == 0))[0][0])
     bad = np.concatenate([bad[k:k + 1], np.delete(bad, k, axis=0)])
@@ -189,4 +189,48 @@ def test_tuning_table_loads_into_a_valid_config():
     split = bool(cfg.flags & pald.BATCH_SPLIT_PASS1)
     assert len(items) > 0 and ((tiles1 == 0).all() if split else (tiles1 > 0).all())
     tcfg = pald.load_tuning(timestamps=True)
-    assert tcfg.flags == pald.BATCH_TIMESTAMPS | (pald.BATCH_SPLIT_PASS1 if split else 0)
+    assert tcfg.flags == pald.BATCH_TIMESTAMPS | (pald.BATCH_SPLIT_PASS1 if split else pald.BATCH_ONE_LAUNCH)
+
+
+def test_builtin_config_is_the_tuned_table():
+    """A NULL config (and a config with every field 0) gives the queue of the autotuner's
+    record, compiled into the library: with the split form on gfx950, no matrix has
+    pass-1 items in the persistent queue."""
+    import json
+    import os
+
+    sizes = SIZE_MIXES["batch_like"]
+    with open(pald.TUNING_PATH) as f:
+        rec = json.load(f)
+    tuned = pald.load_tuning()
+    for grid in (64, 1024):
+        items0, tiles0 = pald.batch_queue(sizes, grid)  # NULL config
+        items1, tiles1 = pald.batch_queue(sizes, grid, config=tuned)
+        items2, tiles2 = pald.batch_queue(sizes, grid, config=pald.make_batch_config(split_pass1=None))
+        assert np.array_equal(items0, items1) and np.array_equal(tiles0, tiles1)
+        assert np.array_equal(items0, items2) and np.array_equal(tiles0, tiles2)
+        if rec.get("split_pass1"):
+            assert (tiles0 == 0).all()
+            assert (items0[:, 1] == 1).all()
+    assert os.path.exists(pald.TUNING_PATH)
+
+
+def test_launch_form_flags():
+    sizes = [40, 300]
+    one = pald.make_batch_config(split_pass1=False)
+    split = pald.make_batch_config(split_pass1=True)
+    _, t_one = pald.batch_queue(sizes, 8, config=one)
+    _, t_split = pald.batch_queue(sizes, 8, config=split)
+    assert (t_one > 0).all() and (t_split == 0).all()
+    both = pald.make_batch_config()
+    both.flags = pald.BATCH_SPLIT_PASS1 | pald.BATCH_ONE_LAUNCH
+    with pytest.raises(pald.PaldError):
+        pald.batch_queue(sizes, 8, config=both)
+
+
+def test_generated_tuned_header_matches_the_records():
+    """csrc/tuned_gfx950.h is what build.py writes from the tuning records."""
+    from paper_2307_16652_amd import build
+
+    with open(build.TUNED_HEADER) as f:
+        assert f.read() == build.tuned_header_text()

@@ -62,18 +62,30 @@ def check_all(mats, Us, Cs, every=1, what=""):
 RAGGED = [2, 3, 5, 17, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 257, 300]
 
 
-def test_ragged_sizes():
+def form_config(form):
+    """None (the library's built-in, tuned configuration) or an explicit launch form."""
+    from paper_2307_16652_amd import pald
+
+    return None if form == "builtin" else pald.make_batch_config(split_pass1=(form == "split"))
+
+
+FORMS = ["builtin", "one_launch", "split"]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_ragged_sizes(form):
     mats = make_batch(RAGGED, seed=1)
-    log(f"[batched] ragged {RAGGED}")
-    _, _, Us, Cs = run_batch(mats)
-    check_all(mats, Us, Cs, what="ragged")
+    log(f"[batched] ragged {RAGGED}, {form}")
+    _, _, Us, Cs = run_batch(mats, config=form_config(form))
+    check_all(mats, Us, Cs, what=f"ragged {form}")
 
 
-def test_tie_heavy_and_duplicates():
+@pytest.mark.parametrize("form", FORMS)
+def test_tie_heavy_and_duplicates(form):
     sizes = [4, 9, 64, 70, 150]
     mats = make_batch(sizes, seed=2, kind="grid")
-    _, _, Us, Cs = run_batch(mats)
-    check_all(mats, Us, Cs, what="grid")
+    _, _, Us, Cs = run_batch(mats, config=form_config(form))
+    check_all(mats, Us, Cs, what=f"grid {form}")
 
 
 @pytest.mark.parametrize("chunks", [2, 3, 7])
@@ -192,7 +204,7 @@ def test_unaligned_base_pointer():
     from paper_2307_16652_amd import pald
 
     mats = make_batch([36, 64, 100], seed=9)
-    plan = pald.BatchPlan([m.shape[0] for m in mats])
+    plan = pald.BatchPlan([m.shape[0] for m in mats], config=pald.make_batch_config(split_pass1=False))
     flat = np.concatenate([m.reshape(-1) for m in mats])
     buf = torch.zeros(flat.size + 1, dtype=torch.float32, device="cuda")
     buf[1:] = torch.from_numpy(flat).cuda()
@@ -264,13 +276,14 @@ def test_split_pass1_graph_timestamps_unaligned_no_u(buckets):
 
 
 def test_cohesion_batched_convenience():
-    """pald.cohesion_batched with the tuned table (default) and with the library
-    defaults: oracle parity and the same results from both."""
+    """pald.cohesion_batched with the autotuner's record read at run time (default)
+    and with a NULL config (the library's built-in table, compiled from the same
+    record): oracle parity and bit-identical results."""
     import torch
 
     from paper_2307_16652_amd import pald
 
-    mats = make_batch([70, 3, 129, 40], seed=16)
+    mats = make_batch([70, 3, 129, 40, 1000, 513], seed=16)
     tuned = pald.cohesion_batched([torch.from_numpy(m).cuda() for m in mats])
     plain = pald.cohesion_batched([torch.from_numpy(m).cuda() for m in mats], config=None)
     torch.cuda.synchronize()
@@ -292,7 +305,7 @@ def test_config_batch_2000_sampled():
     log(f"[batched] generated 2000 matrices in {time.time() - t0:.1f}s")
     from paper_2307_16652_amd import pald
 
-    _, _, Us, Cs = run_batch(mats, config=pald.load_tuning())  # the benchmark's configuration
+    _, _, Us, Cs = run_batch(mats, config=None)  # the benchmark's: the library's built-in configuration
     log("[batched] run done; checking")
     err = check_all(mats, Us, Cs, every=20, what="batch2000")
     log(f"[batched] max rel err {err:.3e} over the 100 oracle matrices")

@@ -252,15 +252,30 @@ def test_config_mixture8d_n4096_full():
     log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
 
 
+def grid3d_oracle_rows(n: int = 16384, k: int = 256):
+    """The benchmark's seeded sample of oracle rows (the rows bench.py times the
+    oracle on: default_rng(123), k distinct rows) plus rows 0 and n - 1."""
+    rows = np.random.default_rng(123).choice(n, size=k, replace=False)
+    return np.unique(np.concatenate([[0, n - 1], rows]))
+
+
 def test_config_grid3d_n16384_sampled():
-    """The benchmark's workload and launch configuration; oracle on sampled rows."""
+    """The benchmark's workload and launch configuration against the oracle on the
+    config's 256 seeded rows (plus the first and last), for the compensated and
+    the FP64-accumulate forms."""
     D = synth.grid3d()
-    rows = np.sort(np.random.default_rng(3).choice(16384, size=24, replace=False))
-    rows = np.concatenate([[0, 16383], rows])
-    U, C, err = parity(D, "grid3d n=16384 (26 oracle rows)", rows=rows)
+    rows = grid3d_oracle_rows()
+    log(f"[parity] grid3d n=16384: oracle on {rows.size} rows")
+    Uo, Co = oracle.pald_rows(D, rows)
+    U, C = gpu_cohesion(D)
+    assert_u_equal(U[rows], Uo, "grid3d n=16384 U rows")
+    err = assert_c_close(C[rows], Co, what="grid3d n=16384 C rows")
     check_invariants(U, C, "grid3d")
-    _, _, err64 = parity(D, "grid3d n=16384 (26 oracle rows), FP64 form", rows=rows, accum="f64")
-    log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
+    del U, C
+    U64, C64 = gpu_cohesion(D, accum="f64")
+    assert_u_equal(U64[rows], Uo, "grid3d n=16384 U rows, FP64 form")
+    err64 = assert_c_close(C64[rows], Co, what="grid3d n=16384 C rows, FP64 form")
+    log(f"  {rows.size} rows: max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
 
 
 def test_diagonal_identity_without_coincident_points():

@@ -135,6 +135,37 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd,
                           void *ws, size_t ws_bytes,
                           void *stream, const pald_options *opt);
 
+/* Bytes of the fixed device workspace behind pald_cohesion_noalloc (64 MiB per
+ * GPU, held by the library from the first call on that GPU until the process
+ * ends). */
+#define PALD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * pald_cohesion without a workspace argument, for callers that cannot allocate
+ * device memory: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It calls no hipMalloc, hipFree or other allocating
+ * routine; its workspace is a device array of PALD_NOALLOC_SCRATCH_BYTES
+ * inside the library, one per GPU.
+ *   D, U, C, stream, opt  as for pald_cohesion (the caller still owns and
+ *                         passes the inputs and outputs)
+ * The plan is the one pald_cohesion uses with `opt`, except that an automatic
+ * y split (y_chunks = 0) is lowered until its float64 partial sums fit; C
+ * then differs from pald_cohesion's in rounding only (same error bound).
+ * With default options every n <= 4096 fits.
+ * Errors: as pald_cohesion; PALD_ERR_ARG also when the workspace the plan
+ * needs exceeds PALD_NOALLOC_SCRATCH_BYTES; PALD_ERR_UNSUPPORTED for the
+ * triplet and hybrid variants; PALD_ERR_DEVICE if the array's address cannot
+ * be looked up (done once per GPU, on the first call made with it current).
+ * Every call on one GPU uses the same array and leaves it holding that call's
+ * intermediates: calls that can overlap in time on one GPU (different streams
+ * or host threads without ordering between them) race and give wrong results,
+ * so the caller must serialise them.
+ */
+pald_status pald_cohesion_noalloc(const float *D, int64_t n, int64_t ldd,
+                                  int32_t *U, int64_t ldu,
+                                  float *C, int64_t ldc,
+                                  void *stream, const pald_options *opt);
+
 /*
  * Validates D against the input contract.  Synchronous: enqueues a check on
  * `stream`, waits for it and returns PALD_OK or PALD_ERR_INPUT.  If

@@ -344,6 +344,36 @@ pald_status run_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int
 
 }  // namespace
 
+// ---- fixed workspace of pald_cohesion_noalloc -------------------------------
+// One array per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// noalloc_scratch() looks up its device address once per device and every use
+// goes through that address.
+static __device__ __align__(256) unsigned char scratch[PALD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made on that device).
+pald_status noalloc_scratch(char **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PALD_ERR_DEVICE;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PALD_ERR_DEVICE;
+        addr[dev] = ptr;
+    }
+    *out = static_cast<char *>(addr[dev]);
+    return PALD_OK;
+}
+
+}  // namespace
+
 // ============================================================================
 extern "C" {
 
@@ -402,6 +432,27 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
     if (ws_bytes < p.bytes) return PALD_ERR_ARG;
     return run_cohesion(D, n, ldd, U, ldu, C, ldc, static_cast<char *>(ws), p, o, s);
+}
+
+pald_status pald_cohesion_noalloc(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C,
+                                  int64_t ldc, void *stream, const pald_options *opt) {
+    Opts o;
+    if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
+    if (!D || !C || n < 2 || ldd < n || ldc < n || (U && ldu < n)) return PALD_ERR_ARG;
+    if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID) return PALD_ERR_UNSUPPORTED;
+    o.variant = PALD_VARIANT_PAIRWISE;  // AUTO runs pairwise here
+    Plan p;
+    if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;
+    // an automatic y split is lowered until its partial sums fit
+    for (int32_t yc = p.y_chunks - 1; p.bytes > PALD_NOALLOC_SCRATCH_BYTES && o.y_chunks == 0 && yc >= 1; --yc) {
+        Opts oy = o;
+        oy.y_chunks = yc;
+        if (pald_status st = make_plan(n, oy, p); st != PALD_OK) return st;
+    }
+    if (p.bytes > PALD_NOALLOC_SCRATCH_BYTES) return PALD_ERR_ARG;
+    char *base = nullptr;
+    if (pald_status st = noalloc_scratch(&base); st != PALD_OK) return st;
+    return run_cohesion(D, n, ldd, U, ldu, C, ldc, base, p, o, (hipStream_t)stream);
 }
 
 pald_status pald_check_input(const float *D, int64_t n, int64_t ldd, void *ws, size_t ws_bytes, void *stream,

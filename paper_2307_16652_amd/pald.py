@@ -36,7 +36,7 @@ EXPORTED = (
     "pald_batch_timestamps", "pald_batch_queue", "pald_batch_plan_destroy",
     "pald_batch_graph_create", "pald_batch_graph_launch", "pald_batch_graph_destroy",
     "pald_timings_collect", "pald_distances", "pald_local_depths", "pald_strong_ties",
-    "pald_graph_distances_workspace_bytes", "pald_graph_distances",
+    "pald_graph_distances_workspace_bytes", "pald_graph_distances", "pald_cohesion_noalloc",
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
@@ -146,6 +146,8 @@ def load_library(path: str | None = None):
     lib.pald_focus_sizes.restype = i32
     lib.pald_cohesion.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, sz, vp, opt]
     lib.pald_cohesion.restype = i32
+    lib.pald_cohesion_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, opt]
+    lib.pald_cohesion_noalloc.restype = i32
     lib.pald_check_input.argtypes = [vp, i64, i64, vp, sz, vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.pald_check_input.restype = i32
     cfgp = ctypes.POINTER(BatchConfig)
@@ -287,6 +289,29 @@ def cohesion(D, *, variant: str = "auto", accum: str = "compensated", y_chunks: 
         C.data_ptr(), C.stride(0), ws.data_ptr(), ws.numel(),
         _stream_ptr(D.device), ctypes.byref(o))
     _check(st, "pald_cohesion")
+    return U, C
+
+
+#: bytes of the library's fixed per-GPU workspace used by cohesion_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def cohesion_noalloc(D, *, accum: str = "compensated", y_chunks: int = 0, z_chunks: int = 0,
+                     timing: bool = False, out_u=None, out_c=None):
+    """(U, C) like cohesion(), through pald_cohesion_noalloc: no workspace is allocated
+    (the library's fixed per-GPU array serves as one).  out_u / out_c given: nothing
+    is allocated here either.  Pairwise variant only; calls on one GPU must not overlap."""
+    torch = _torch()
+    n, ldd = _check_matrix(D)
+    o = make_options(variant="pairwise", accum=accum, y_chunks=y_chunks, z_chunks=z_chunks,
+                     timing=timing)
+    U = out_u
+    C = out_c if out_c is not None else torch.empty((n, n), dtype=torch.float32, device=D.device)
+    st = load_library().pald_cohesion_noalloc(
+        D.data_ptr(), n, ldd,
+        U.data_ptr() if U is not None else None, U.stride(0) if U is not None else 0,
+        C.data_ptr(), C.stride(0), _stream_ptr(D.device), ctypes.byref(o))
+    _check(st, "pald_cohesion_noalloc")
     return U, C
 
 

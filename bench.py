@@ -13,13 +13,20 @@ point in each of the two defining sums) divided by the time per step.
 
 `roofline` describes the dominant kernel (pass 2, cohesion), whose launches
 are timed with HIP events on the stream they run on.  Its algorithmic work is
-4 VALU lane-operations per cohesion term (x, y, z), y != x -- the paper's
-count for the cohesion loop, three comparisons and one accumulate per pair
-and third point (Section 4, Thm 1) -- i.e. 4 n^2 (n-1) per step, set against
-the VALU issue peak of 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T
-lane-ops/s.  `traffic` is the HBM bytes per launch measured by rocprofv3
-(profiles/*.traffic.json), reported only while the kernel source is the one
-that was profiled.
+4 lane-operations per cohesion term (x, y, z), y != x: the three comparisons
+the tie-exact term needs ([t <= a], [t <= b], [t < b] with t = d_xz, a = d_xy,
+b = d_zy) and one accumulate -- 4 n^2 (n-1) per step.  The peak is the vector
+issue capacity of the chip: 256 CUs x 4 SIMDs x 64 lanes x 2 wave64
+instructions per 4 cycles x 2.4 GHz = 78.64 T lane-ops/s (the published
+157.3 TFLOP/s float32 vector rate, an FMA counting 2).  `bench.py
+--valu-probe` measures what each instruction class actually sustains:
+float32 add/mul/fma and simple integer ops issue at about 2.2 cycles per wave
+instruction, compares, min/max and selects at about 4.2 (half rate, 39.32 T
+lane-ops/s), with float32 additions issuing beside them.  `compare_pipe`
+sets the method's comparisons (3 per term) against that half-rate class.
+`traffic`, and the issued vector instructions per term, are from rocprofv3
+(profiles/pass2_cohesion__grid3d_n16384.json), reported only while the
+kernel sources are the ones that were profiled.
 
 `cpu_baseline` is the FP64 oracle on the host cores for a bounded sample of
 rows of the same matrix (2 n^2 comparison terms per row).
@@ -40,8 +47,12 @@ if ROOT not in sys.path:
 
 N = 16384
 SEED = 3
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3216 T lane-ops/s
+# vector issue capacity: 2 wave64 instructions per SIMD per 4 cycles
+VALU_PEAK_TOPS = 256 * 4 * 64 * (2 / 4) * 2.4e9 / 1e12  # 78.64 T lane-ops/s
+# compares, min/max, selects: one wave64 instruction per SIMD per 4 cycles
+COMPARE_PEAK_TOPS = 256 * 4 * 64 * (1 / 4) * 2.4e9 / 1e12  # 39.32 T lane-ops/s
 PASS2_OPS_PER_TERM = 4
+PASS2_COMPARES_PER_TERM = 3
 # Pass 1 counts 64 z per instruction pair: per (pair, 64 z) one vector min +
 # one vector compare and one scalar popcount + one scalar add.  Each pipe
 # issues one wave instruction per SIMD every 4 cycles (vector: 64 lanes on
@@ -50,20 +61,71 @@ PASS1_INSTR_PER_64 = 2
 PASS1_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4  # wave instructions/s per pipe
 
 
-def measured_traffic(kernel_file: str, record: str):
-    """HBM bytes per launch from a rocprofv3 record, or None if the kernel changed since."""
+PROFILE_SOURCES = ("paper_2307_16652_amd/csrc/pairwise.hpp", "paper_2307_16652_amd/csrc/pald_api.hip")
+
+
+def sources_digest(files=PROFILE_SOURCES) -> str:
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", record)
-    src = os.path.join(ROOT, kernel_file)
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profile_record(record: str):
+    """A rocprofv3 counter record from profiles/, or None if absent or if the
+    kernel sources changed since it was taken."""
     try:
-        with open(path) as f:
+        with open(os.path.join(ROOT, "profiles", record)) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
+    except (OSError, ValueError):
         return None
-    return rec["traffic_bytes"] if rec.get("kernel_source_sha256") == digest else None
+    return rec if rec.get("sources_sha256") == sources_digest() else None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def valu_probe(waves=(8, 4), iters: int = 20000) -> dict:
+    """SIMD cycles per wave64 vector instruction of each probe class (libpald_probe.so)."""
+    import ctypes
+
+    from paper_2307_16652_amd import build as pald_build
+
+    if not os.path.exists(pald_build.PROBE_LIB):
+        pald_build.build_probe()
+    lib = ctypes.CDLL(pald_build.PROBE_LIB)
+    lib.pald_probe_valu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.pald_probe_valu.restype = ctypes.c_int32
+    names = ["v_add_f32", "v_fma_f32", "v_add_u32", "v_and_b32", "v_min_u32", "v_min_f32", "v_cmp_lt_u32_e64",
+             "v_cmp_le_f32_e64", "v_cndmask_b32_e64", "v_addc_co_u32_e64", "v_cmp_lt_u32_e64 + v_add_f32",
+             "v_min_u32 + v_add_f32", "v_min_u32 + v_and_b32", "pass-2 block: 16 compares + 16 masked v_add_f32"]
+    assert lib.pald_probe_classes() == len(names)
+    out = {"unit": "SIMD cycles per wave64 vector instruction (at the measured shader clock)", "classes": {}}
+    buf = (ctypes.c_double * 4)()
+    for k, name in enumerate(names):
+        row = {}
+        for w in waves:
+            rc = lib.pald_probe_valu(k, w, iters, buf)
+            if rc != 0:
+                raise RuntimeError(f"pald_probe_valu({k}, {w}) failed: {rc}")
+            row[f"{w}_waves_per_simd"] = round(buf[0], 3)
+            row[f"clock_ghz_{w}"] = round(buf[1], 3)
+        out["classes"][name] = row
+        progress(f"probe {name}: {row}")
+    return out
 
 
 def progress(msg: str):
@@ -89,6 +151,7 @@ def cpu_baseline(D: np.ndarray, workload: str = "grid3d", rows_wanted: int = 256
         "value": round(value, 4),
         "unit": "G triplet comparisons/s",
         "cores": threads,
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": f"{k} seeded random rows of U and C of the n={n} {workload} matrix "
                   f"(2*n^2 terms per row), {t:.1f} s wall",
@@ -338,6 +401,11 @@ def main():
                     help="batched: skip timing the one-launch form beside the tuned split form")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the distance front end, local depths and strong-tie measurements")
+    ap.add_argument("--variant", default="auto", choices=["auto", "pairwise", "triplet", "hybrid"],
+                    help="algorithm of the timed step (default: the library's tuned choice, pairwise)")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="instead of the benchmark, measure the vector issue rate of each instruction class "
+                         "the kernels use and print it as one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise kernel that reads and writes 1 GiB, so a "
                          "counter profile can scale FETCH_SIZE / WRITE_SIZE")
@@ -360,6 +428,9 @@ def main():
 
         pald_build.build()
     pald.load_library()
+    if args.valu_probe:
+        print(json.dumps({"valu_probe": valu_probe()}), flush=True)
+        return
 
     n = args.n
     dev = torch.device("cuda:0")
@@ -379,12 +450,12 @@ def main():
     else:
         D = synth.workload(args.workload, n=n, seed=seed)
         Dg = torch.from_numpy(D).to(dev)
-    ws = pald.workspace(n, dev)
+    ws = pald.workspace(n, dev, variant=args.variant)
     U = torch.empty((n, n), dtype=torch.int32, device=dev)
     C = torch.empty((n, n), dtype=torch.float32, device=dev)
 
     def step(timing: bool):
-        pald.cohesion(Dg, ws=ws, out_u=U, out_c=C, timing=timing)
+        pald.cohesion(Dg, ws=ws, out_u=U, out_c=C, timing=timing, variant=args.variant)
 
     progress(f"warmup x{args.warmup}")
     for _ in range(args.warmup):
@@ -406,25 +477,34 @@ def main():
     progress(f"{ms_per_step:.1f} ms/step, {value:.1f} G/s; kernels {kt}")
 
     # per-step kernel time (a large grid runs as several launches per step)
-    p2_ms = kt["pass2_cohesion"][0] / args.steps
-    p1_ms = kt["pass1_focus"][0] / args.steps
-    p2_launches = kt["pass2_cohesion"][1] // args.steps
-    p2_ops = PASS2_OPS_PER_TERM * n * n * (n - 1)
-    p2_achieved = p2_ops / (p2_ms / 1e3) / 1e12
+    roofline = None
+    if "pass2_cohesion" in kt:
+        p2_ms = kt["pass2_cohesion"][0] / args.steps
+        p2_launches = kt["pass2_cohesion"][1] // args.steps
+        terms = n * n * (n - 1)
+        p2_achieved = PASS2_OPS_PER_TERM * terms / (p2_ms / 1e3) / 1e12
+        cmp_achieved = PASS2_COMPARES_PER_TERM * terms / (p2_ms / 1e3) / 1e12
+        rec = profile_record("pass2_cohesion__grid3d_n16384.json") if (n, args.workload) == (N, "grid3d") else None
+        issued = rec["valu_insts"] * 64 / terms if rec else None
+        roofline = {
+            "bound": "alu",
+            "achieved": round(p2_achieved, 3),
+            "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "T VALU lane-ops/s",
+            "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
+            "traffic": rec["traffic_bytes"] if rec else None,
+            "kernel": "pass2_cohesion",
+            "kernel_ms": round(p2_ms, 3),
+            "launches_per_step": p2_launches,
+            "ops_per_term": PASS2_OPS_PER_TERM,
+            "issued_lane_ops_per_term": round(issued, 3) if issued else None,
+            "useful_fraction": round(PASS2_OPS_PER_TERM / issued, 4) if issued else None,
+            "compare_pipe": {"achieved": round(cmp_achieved, 3), "peak": round(COMPARE_PEAK_TOPS, 3),
+                             "unit": "T compare lane-ops/s", "frac": round(cmp_achieved / COMPARE_PEAK_TOPS, 4),
+                             "compares_per_term": PASS2_COMPARES_PER_TERM},
+        }
+    p1_ms = kt["pass1_focus"][0] / args.steps if "pass1_focus" in kt else None
     p1_units = (n * (n + 1) / 2) * n  # (pair x <= y, z)
-    roofline = {
-        "bound": "alu",
-        "achieved": round(p2_achieved, 3),
-        "peak": round(VALU_PEAK_TOPS, 3),
-        "unit": "T VALU lane-ops/s",
-        "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
-        "traffic": measured_traffic("paper_2307_16652_amd/csrc/pairwise.hpp",
-                                    "pass2_cohesion__grid3d_n16384.traffic.json") if (n, args.workload) == (N, "grid3d")
-        else None,
-        "kernel": "pass2_cohesion",
-        "kernel_ms": round(p2_ms, 3),
-        "launches_per_step": p2_launches,
-    }
     kernels = {k: round(v[0] / args.steps, 3) for k, v in kt.items()}
 
     extra = {}
@@ -449,9 +529,10 @@ def main():
     if not args.no_comparators:
         extra["variants_n4096"] = variants_bench(dev)
         progress(f"variants: {extra['variants_n4096']}")
-    p1_bound_ms = PASS1_INSTR_PER_64 * p1_units / 64 / PASS1_ISSUE_PEAK * 1e3
-    extra["pass1_focus"] = {"ms": round(p1_ms, 3), "G_pair_z_per_s": round(p1_units / (p1_ms / 1e3) / 1e9, 1),
-                            "issue_bound_ms": round(p1_bound_ms, 3), "issue_frac": round(p1_bound_ms / p1_ms, 4)}
+    if p1_ms:
+        p1_bound_ms = PASS1_INSTR_PER_64 * p1_units / 64 / PASS1_ISSUE_PEAK * 1e3
+        extra["pass1_focus"] = {"ms": round(p1_ms, 3), "G_pair_z_per_s": round(p1_units / (p1_ms / 1e3) / 1e9, 1),
+                                "issue_bound_ms": round(p1_bound_ms, 3), "issue_frac": round(p1_bound_ms / p1_ms, 4)}
     if not args.no_pipeline:
         progress("pipeline: distances, local depths, strong ties")
         extra["pipeline"] = pipeline_bench(dev, n, Dg, C, args.workload)

@@ -178,6 +178,72 @@ pald_status pald_check_input(const float *D, int64_t n, int64_t ldd,
                              uint32_t *flags_out);
 
 /* ---------------------------------------------------------------------------
+ * Blocks of rows.  Row x of U and of C depends on all of D but on row x of
+ * the focus sizes only (Section 3, Eq. (fxz): c_xz sums over y the terms of
+ * the foci of x and y), so the rows split over devices -- or over panels of
+ * one device -- with D the only shared input.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes pald_cohesion_rows needs for `rows` rows of an n x n
+ * problem (the weights of the block, transposed); 0 if n < 2, rows < 1,
+ * rows > n or opt is invalid. */
+size_t pald_rows_workspace_bytes(int64_t n, int64_t rows, const pald_options *opt);
+
+/*
+ * Rows x0 <= x < x1 of U and of C (the same values pald_cohesion gives for
+ * these rows: U exactly, C within the same error bound).
+ *   D     [n x ldd]  float32 distances, device, read only (every row is read)
+ *   U     [(x1-x0) x ldu] int32 output, device, or NULL: row x at U + (x-x0) ldu
+ *   C     [(x1-x0) x ldc] float32 output, device: row x at C + (x-x0) ldc
+ *   ws    device workspace of at least pald_rows_workspace_bytes(n, x1-x0, opt)
+ *         bytes, 256-byte aligned
+ * Pass 1 counts the focus sizes of the block's pairs (x, y) for every y; pass 2
+ * accumulates only c_xz for x in the block (the whole-matrix pass 2 shares
+ * each compare between c_xz and c_zx, which a block of rows cannot), in
+ * float32 runs of at most 12 additions folded into Kahan sums, reduced in
+ * float64.  Options: variant AUTO or PAIRWISE, compensated accumulation, no
+ * forced splits (else PALD_ERR_UNSUPPORTED).
+ * Errors: PALD_ERR_ARG for null D/C/ws, n < 2, a leading dimension < n,
+ * x0 < 0, x1 <= x0, x1 > n, a small or misaligned ws.
+ */
+pald_status pald_cohesion_rows(const float *D, int64_t n, int64_t ldd,
+                               int64_t x0, int64_t x1,
+                               int32_t *U, int64_t ldu,
+                               float *C, int64_t ldc,
+                               void *ws, size_t ws_bytes,
+                               void *stream, const pald_options *opt);
+
+/*
+ * Out of core: U and C of a distance matrix that stays in host memory, for
+ * n beyond what fits in device memory (D alone is 4 n^2 bytes; the whole-
+ * matrix call keeps D, U, C and W resident, 16 n^2 bytes), in panels of rows
+ * sized to a device workspace of ws_bytes.  Per panel of P rows the library
+ * copies the panel's rows of D to the device, streams D in blocks of P rows
+ * twice (pass 1, then pass 2, each block read once per pass), and copies the
+ * panel's rows of U and C back.  U equals pald_cohesion's exactly; C is
+ * accumulated per block of y (float32 runs and Kahan sums as in
+ * pald_cohesion_rows) and summed over the blocks in float64, within the same
+ * error bound.  Host traffic: 8 n^2 (n / P) bytes of D plus 8 n^2 of U and C.
+ *   D_host  [n x ldd]  float32, host memory (pinned memory copies fastest)
+ *   U_host  [n x ldu]  int32 output, host memory, or NULL
+ *   C_host  [n x ldc]  float32 output, host memory
+ *   ws      device workspace, 256-byte aligned, of at least
+ *           pald_ooc_workspace_bytes(n, 16) bytes; the panel height P is the
+ *           largest multiple of 16 (at most n) whose pald_ooc_workspace_bytes
+ *           fits in ws_bytes
+ * Synchronous: returns once the results are in host memory (work runs on
+ * `stream`, which is synchronised).  Options as pald_cohesion_rows.
+ * Errors: PALD_ERR_ARG for null D_host/C_host/ws, n < 2, a leading dimension
+ * < n, a small or misaligned ws; PALD_ERR_DEVICE for a failed copy or launch.
+ */
+size_t pald_ooc_workspace_bytes(int64_t n, int64_t panel_rows);
+pald_status pald_cohesion_ooc(const float *D_host, int64_t n, int64_t ldd,
+                              int32_t *U_host, int64_t ldu,
+                              float *C_host, int64_t ldc,
+                              void *ws, size_t ws_bytes,
+                              void *stream, const pald_options *opt);
+
+/* ---------------------------------------------------------------------------
  * Before and after the two passes.
  * ------------------------------------------------------------------------- */
 
@@ -407,8 +473,9 @@ void pald_batch_graph_destroy(pald_batch_graph *graph);
  * 1 weight preparation, 2 pass-2 cohesion, 3 cross-chunk finalize,
  * 4 batched persistent kernel, 5 triplet pass 1, 6 triplet pass 2,
  * 7 triplet finalize, 8 distances, 9 local depths, 10 strong-tie count and
- * scan, 11 strong-tie fill, 12 graph distances.  Returns the number of kinds
- * defined (13).
+ * scan, 11 strong-tie fill, 12 graph distances, 13 row-block pass 1,
+ * 14 row-block pass 2 (with its finalize), 15 host <-> device copies of the
+ * out-of-core mode.  Returns the number of kinds defined (16).
  */
 int32_t pald_timings_collect(double *total_ms, int64_t *count, int32_t kinds);
 

@@ -45,6 +45,9 @@ def sources():
     return [os.path.join(CSRC, f) for f in ("pald_api.hip", "frontend_api.hip")]
 
 
+PROBE_LIB = os.path.join(PKG, "libpald_probe.so")
+
+
 TUNING = os.path.join(PKG, "tuning")
 TUNED_HEADER = os.path.join(CSRC, "tuned_gfx950.h")
 _VARIANT_ENUM = {"pairwise": "PALD_VARIANT_PAIRWISE", "triplet": "PALD_VARIANT_TRIPLET",
@@ -138,7 +141,22 @@ def build(verbose: bool = False) -> str:
     if out.strip() and verbose:
         print(out)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """libpald_probe.so: the vector-unit issue-rate probes behind the roofline's
+    peak (bench.py --valu-probe); measurement support, not part of the method."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, os.path.join(CSRC, "valu_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stdout}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

@@ -181,11 +181,26 @@ __global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void b
 #ifndef PALD_BATCH_LEAN_FEW_SGPR
 #define PALD_BATCH_LEAN_FEW_SGPR 0
 #endif
-__global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_pass2_lean_kernel(
+// The lean kernel's tile: 64 x 64 with 2 x 4 pairs per thread (512 threads,
+// about 100 VGPRs), the single-matrix pass-2 shape -- more waves per SIMD than
+// the general kernel's 4 x 4 pairs, so the compares of one wave issue beside
+// the additions of another.
+#ifndef PALD_BATCH_LEAN_RX
+#define PALD_BATCH_LEAN_RX 2
+#endif
+#ifndef PALD_BATCH_LEAN_MIN_WAVES
+#define PALD_BATCH_LEAN_MIN_WAVES 4
+#endif
+#ifndef PALD_BATCH_LEAN_KY
+#define PALD_BATCH_LEAN_KY 24
+#endif
+using BatchLeanP2 = Pass2Cfg<BATCH_P2_T, PALD_BATCH_LEAN_RX, PALD_BATCH_LEAN_KY>;
+constexpr int BATCH_LEAN_THREADS = BatchLeanP2::NT;
+__global__ __launch_bounds__(BATCH_LEAN_THREADS, PALD_BATCH_LEAN_MIN_WAVES) void batched_pass2_lean_kernel(
     const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
     float *__restrict__ C, const float *__restrict__ Wr, uint32_t *__restrict__ ctr, uint64_t *__restrict__ stamps,
     int32_t d_aligned) {
-    __shared__ uint4 sm[BatchP2::LDS_VEC];
+    __shared__ uint4 sm[BatchLeanP2::LDS_VEC];
     __shared__ int32_t s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&ctr[0], 1u);
@@ -198,7 +213,7 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
         const bool vec_d = d_aligned && mats[mi].vec_d;
         int32_t bx, bz;
         tri_tile(item.z, bx, bz);
-        pass2_tile<BATCH_P2_T, BATCH_P2_RX, BATCH_P2_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR>(
+        pass2_tile<BATCH_P2_T, PALD_BATCH_LEAN_RX, PALD_BATCH_LEAN_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR, true>(
             opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw, Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0, n,
             vec_d, true);
         if (stamps && threadIdx.x == 0) {

@@ -33,8 +33,9 @@ inline pald_status launch_status() {
 // Kinds: 0 pass-1 focus sizes, 1 weights, 2 pass-2 cohesion, 3 finalize,
 // 4 batched persistent kernel, 5-7 triplet pass 1 / pass 2 / finalize,
 // 8 distances, 9 local depths, 10 strong-tie count + scan, 11 strong-tie fill,
-// 12 graph distances.
-constexpr int NUM_KINDS = 13;
+// 12 graph distances, 13 row-block pass 1, 14 row-block pass 2, 15 host <->
+// device copies of the out-of-core mode.
+constexpr int NUM_KINDS = 16;
 
 struct TimingRec {
     int kind;

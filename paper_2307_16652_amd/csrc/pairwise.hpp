@@ -179,140 +179,100 @@ __device__ __forceinline__ void focus_mask_flush(int32_t (&c)[32], const uint64_
     c[31] += __builtin_popcountll(k[1]);
 }
 
-// Cohesion terms of one x and four z for one second point y, both directions:
-//   in_j  = [t_j <= min(a, b_j)]
-//   rf_j += in_j ? (t_j < b_j ? wx : whx) : 0          (c_xz, focus of x and y)
-//   rr_j += in_j ? (t_j < a   ? wz_j : whz_j) : 0      (c_zx, focus of z and y)
-// with a = d_xy, b_j = d_z_j y, t_j = d_x z_j (all as keys), wx = W_xy,
-// wz_j = W_z_j y and wh = w / 2.  One block, so that every compare mask is read at least two
-// instructions after it is written (the wait states a vector read of a
-// vector-written scalar register needs) and the four pairs interleave; the
-// compiler's own schedule funnels the masks through one or two registers.
-// FEW_SGPR: the two select masks of a pair rotate through two register sets,
-// so a block holds 8 scalar-register pairs of masks instead of 12 (for
-// kernels short of scalar registers); the default keeps all 12 live.
-// Registers only, no memory access; EXEC is back to its entry value at exit.
-template <bool FEW_SGPR>
+// Cohesion terms of one x and four z for one second point y, both
+// directions, as EXEC-masked additions of half weights.  With the keys
+// t_j = d_x z_j, a = d_xy, b_j = d_z_j y and the half weights hx = W_xy / 2,
+// hz_j = W_z_j y / 2, pair j takes four compares
+//     i = [t_j <= a],  j = [t_j <= b_j],  p = [t_j < b_j],  q = [t_j < a]
+// and adds
+//     rf_j += hx    under i & j, and again under i & p   (c_xz: W_xy if t < b, W_xy/2 on a tie)
+//     rr_j += hz_j  under i & j, and again under j & q   (c_zx: W_zy if t < a, W_zy/2 on a tie)
+// i & j is focus membership, [t <= min(a, b)]; p implies j and q implies i,
+// so i & p and j & q are membership together with the strict order.
+//
+// The compares run under the caller's EXEC and leave 0 in inactive lanes, so
+// no mask enables a lane that was off; the scalar unit sets EXEC to each mask
+// in turn and restores `full` (the caller's EXEC) at the end of a group of G
+// pairs.  On gfx950 compares take the vector unit about 4 cycles per wave
+// instruction while float32 additions issue beside them, so four compares and
+// four masked additions cost little more than the compares alone -- less
+// than a min, three compares, two selects of W or W/2 and two additions.
+// G = 4 keeps 16 masks (32 scalar registers) live; G = 2 half of that, for
+// kernels short of scalar registers.  Registers only, no memory access.
+#define PALD_H_CMP(k)                                                                                            \
+    "v_cmp_le_u32_e64 %[i" #k "], %[t" #k "], %[a]\n\t"                                                       \
+    "v_cmp_le_u32_e64 %[j" #k "], %[t" #k "], %[b" #k "]\n\t"                                                 \
+    "v_cmp_lt_u32_e64 %[p" #k "], %[t" #k "], %[b" #k "]\n\t"                                                 \
+    "v_cmp_lt_u32_e64 %[q" #k "], %[t" #k "], %[a]\n\t"
+#define PALD_H_ADD(k)                                                                                            \
+    "s_and_b64 exec, %[i" #k "], %[j" #k "]\n\t"                                                              \
+    "v_add_f32 %[rf" #k "], %[rf" #k "], %[hx]\n\t"                                                           \
+    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hz" #k "]\n\t"                                                     \
+    "s_and_b64 exec, %[i" #k "], %[p" #k "]\n\t"                                                              \
+    "v_add_f32 %[rf" #k "], %[rf" #k "], %[hx]\n\t"                                                           \
+    "s_and_b64 exec, %[j" #k "], %[q" #k "]\n\t"                                                              \
+    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hz" #k "]\n\t"
+#define PALD_H_ADD2(k)                                                                                           \
+    "s_and_b64 exec, %[i" #k "], %[j" #k "]\n\t"                                                              \
+    "v_add_f32 %[rf" #k "], %[rf" #k "], %[hx]\n\t"                                                           \
+    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hz" #k "]\n\t"                                                     \
+    "s_and_b64 exec, %[i" #k "], %[p" #k "]\n\t"                                                              \
+    "v_add_f32 %[gf" #k "], %[gf" #k "], %[hx]\n\t"                                                           \
+    "s_and_b64 exec, %[j" #k "], %[q" #k "]\n\t"                                                              \
+    "v_add_f32 %[gr" #k "], %[gr" #k "], %[hz" #k "]\n\t"
+#define PALD_H_MASKS(k) [i##k] "=&s"(mi[k]), [j##k] "=&s"(mj[k]), [p##k] "=&s"(mp[k]), [q##k] "=&s"(mq[k])
+#define PALD_H_ACC(k) [rf##k] "+v"(rf[k]), [rr##k] "+v"(rr[k])
+#define PALD_H_ACC2(k) [gf##k] "+v"(gf[k]), [gr##k] "+v"(gr[k])
+#define PALD_H_IN(k) [t##k] "v"(t[k]), [b##k] "v"(b[k]), [hz##k] "v"(hz[k])
+template <int G>
 __device__ __forceinline__ void cohesion_terms4(float (&rf)[4], float (&rr)[4], const uint32_t (&t)[4], uint32_t a,
-                                                const uint32_t (&b)[4], float wx, float whx, const float (&wz)[4],
-                                                const float (&whz)[4]) {
-    uint32_t m0, m1, m2, m3;
-    float f0, f1, f2, f3, g0, g1, g2, g3;
-    uint64_t i0, i1, i2, i3, p[4], q[4];
-#define PALD_T4_HEAD_ROT                                                                                            \
-    "v_min_u32 %[m0], %[a], %[b0]\n\t"                                                                          \
-    "v_min_u32 %[m1], %[a], %[b1]\n\t"                                                                          \
-    "v_min_u32 %[m2], %[a], %[b2]\n\t"                                                                          \
-    "v_min_u32 %[m3], %[a], %[b3]\n\t"                                                                          \
-    "v_cmp_le_u32_e64 %[i0], %[t0], %[m0]\n\t"                                                                  \
-    "v_cmp_le_u32_e64 %[i1], %[t1], %[m1]\n\t"                                                                  \
-    "v_cmp_le_u32_e64 %[i2], %[t2], %[m2]\n\t"                                                                  \
-    "v_cmp_le_u32_e64 %[i3], %[t3], %[m3]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[pa], %[t0], %[b0]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[qa], %[t0], %[a]\n\t"                                                                   \
-    "v_cmp_lt_u32_e64 %[pb], %[t1], %[b1]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[qb], %[t1], %[a]\n\t"                                                                   \
-    "v_cndmask_b32_e64 %[f0], %[whx], %[wx], %[pa]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g0], %[whz0], %[wz0], %[qa]\n\t"                                                       \
-    "v_cmp_lt_u32_e64 %[pa], %[t2], %[b2]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[qa], %[t2], %[a]\n\t"                                                                   \
-    "v_cndmask_b32_e64 %[f1], %[whx], %[wx], %[pb]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g1], %[whz1], %[wz1], %[qb]\n\t"                                                       \
-    "v_cmp_lt_u32_e64 %[pb], %[t3], %[b3]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[qb], %[t3], %[a]\n\t"                                                                   \
-    "v_cndmask_b32_e64 %[f2], %[whx], %[wx], %[pa]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g2], %[whz2], %[wz2], %[qa]\n\t"                                                       \
-    "v_cndmask_b32_e64 %[f3], %[whx], %[wx], %[pb]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g3], %[whz3], %[wz3], %[qb]\n\t"
-#define PALD_T4_HEAD_WIDE                                                                                       \
-    "v_min_u32 %[m0], %[a], %[b0]\n\t"                                                                          \
-    "v_min_u32 %[m1], %[a], %[b1]\n\t"                                                                          \
-    "v_min_u32 %[m2], %[a], %[b2]\n\t"                                                                          \
-    "v_min_u32 %[m3], %[a], %[b3]\n\t"                                                                          \
-    "v_cmp_lt_u32_e64 %[p0], %[t0], %[b0]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[q0], %[t0], %[a]\n\t"                                                                   \
-    "v_cmp_le_u32_e64 %[i0], %[t0], %[m0]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[p1], %[t1], %[b1]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[q1], %[t1], %[a]\n\t"                                                                   \
-    "v_cmp_le_u32_e64 %[i1], %[t1], %[m1]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[p2], %[t2], %[b2]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[q2], %[t2], %[a]\n\t"                                                                   \
-    "v_cmp_le_u32_e64 %[i2], %[t2], %[m2]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[p3], %[t3], %[b3]\n\t"                                                                  \
-    "v_cmp_lt_u32_e64 %[q3], %[t3], %[a]\n\t"                                                                   \
-    "v_cmp_le_u32_e64 %[i3], %[t3], %[m3]\n\t"                                                                  \
-    "v_cndmask_b32_e64 %[f0], %[whx], %[wx], %[p0]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g0], %[whz0], %[wz0], %[q0]\n\t"                                                       \
-    "v_cndmask_b32_e64 %[f1], %[whx], %[wx], %[p1]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g1], %[whz1], %[wz1], %[q1]\n\t"                                                       \
-    "v_cndmask_b32_e64 %[f2], %[whx], %[wx], %[p2]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g2], %[whz2], %[wz2], %[q2]\n\t"                                                       \
-    "v_cndmask_b32_e64 %[f3], %[whx], %[wx], %[p3]\n\t"                                                         \
-    "v_cndmask_b32_e64 %[g3], %[whz3], %[wz3], %[q3]\n\t"
-#define PALD_T4_OPERANDS                                                                                        \
-    [m0] "=&v"(m0), [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3), [f0] "=&v"(f0), [f1] "=&v"(f1),          \
-        [f2] "=&v"(f2), [f3] "=&v"(f3), [g0] "=&v"(g0), [g1] "=&v"(g1), [g2] "=&v"(g2), [g3] "=&v"(g3),       \
-        [i0] "=&s"(i0), [i1] "=&s"(i1), [i2] "=&s"(i2), [i3] "=&s"(i3)
-#define PALD_T4_MASKS_ROT [pa] "=&s"(p[0]), [pb] "=&s"(p[1]), [qa] "=&s"(q[0]), [qb] "=&s"(q[1])
-#define PALD_T4_MASKS_WIDE                                                                                      \
-    [p0] "=&s"(p[0]), [p1] "=&s"(p[1]), [p2] "=&s"(p[2]), [p3] "=&s"(p[3]), [q0] "=&s"(q[0]), [q1] "=&s"(q[1]), \
-        [q2] "=&s"(q[2]), [q3] "=&s"(q[3])
-#define PALD_T4_INPUTS                                                                                          \
-    [t0] "v"(t[0]), [t1] "v"(t[1]), [t2] "v"(t[2]), [t3] "v"(t[3]), [a] "v"(a), [b0] "v"(b[0]),               \
-        [b1] "v"(b[1]), [b2] "v"(b[2]), [b3] "v"(b[3]), [wx] "v"(wx), [whx] "v"(whx), [wz0] "v"(wz[0]),       \
-        [wz1] "v"(wz[1]), [wz2] "v"(wz[2]), [wz3] "v"(wz[3]), [whz0] "v"(whz[0]), [whz1] "v"(whz[1]),         \
-        [whz2] "v"(whz[2]), [whz3] "v"(whz[3])
-    {
-        // Adds only in the lanes whose pair is in the focus: EXEC is narrowed to
-        // each pair's membership mask in turn and restored at the end, which
-        // spares the select-with-zero of every term.
-        uint64_t sv;
-        if (FEW_SGPR)
-            asm(PALD_T4_HEAD_ROT
-                "s_and_saveexec_b64 %[sv], %[i0]\n\t"
-                "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
-                "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
-                "s_and_b64 exec, %[sv], %[i1]\n\t"
-                "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
-                "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
-                "s_and_b64 exec, %[sv], %[i2]\n\t"
-                "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
-                "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
-                "s_and_b64 exec, %[sv], %[i3]\n\t"
-                "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
-                "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
-                "s_mov_b64 exec, %[sv]"
-                : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
-                  [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS, PALD_T4_MASKS_ROT
-                : PALD_T4_INPUTS
-                : "scc");
-        else
-            asm(PALD_T4_HEAD_WIDE
-                "s_and_saveexec_b64 %[sv], %[i0]\n\t"
-                "v_add_f32 %[rf0], %[rf0], %[f0]\n\t"
-                "v_add_f32 %[rr0], %[rr0], %[g0]\n\t"
-                "s_and_b64 exec, %[sv], %[i1]\n\t"
-                "v_add_f32 %[rf1], %[rf1], %[f1]\n\t"
-                "v_add_f32 %[rr1], %[rr1], %[g1]\n\t"
-                "s_and_b64 exec, %[sv], %[i2]\n\t"
-                "v_add_f32 %[rf2], %[rf2], %[f2]\n\t"
-                "v_add_f32 %[rr2], %[rr2], %[g2]\n\t"
-                "s_and_b64 exec, %[sv], %[i3]\n\t"
-                "v_add_f32 %[rf3], %[rf3], %[f3]\n\t"
-                "v_add_f32 %[rr3], %[rr3], %[g3]\n\t"
-                "s_mov_b64 exec, %[sv]"
-                : [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]),
-                  [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]), [sv] "=&s"(sv), PALD_T4_OPERANDS, PALD_T4_MASKS_WIDE
-                : PALD_T4_INPUTS
-                : "scc");
+                                                const uint32_t (&b)[4], float hx, const float (&hz)[4],
+                                                uint64_t full) {
+    static_assert(G == 2 || G == 4, "groups of 2 or 4 pairs");
+    uint64_t mi[4], mj[4], mp[4], mq[4];
+    if constexpr (G == 4) {
+        asm(PALD_H_CMP(0) PALD_H_CMP(1) PALD_H_CMP(2) PALD_H_CMP(3)
+            PALD_H_ADD(0) PALD_H_ADD(1) PALD_H_ADD(2) PALD_H_ADD(3)
+            "s_mov_b64 exec, %[full]"
+            : PALD_H_ACC(0), PALD_H_ACC(1), PALD_H_ACC(2), PALD_H_ACC(3),
+              PALD_H_MASKS(0), PALD_H_MASKS(1), PALD_H_MASKS(2), PALD_H_MASKS(3)
+            : [a] "v"(a), [hx] "v"(hx), [full] "s"(full), PALD_H_IN(0), PALD_H_IN(1), PALD_H_IN(2), PALD_H_IN(3)
+            : "scc");
+    } else {
+        asm(PALD_H_CMP(0) PALD_H_CMP(1) PALD_H_ADD(0) PALD_H_ADD(1)
+            "s_mov_b64 exec, %[full]"
+            : PALD_H_ACC(0), PALD_H_ACC(1), PALD_H_MASKS(0), PALD_H_MASKS(1)
+            : [a] "v"(a), [hx] "v"(hx), [full] "s"(full), PALD_H_IN(0), PALD_H_IN(1)
+            : "scc");
+        asm(PALD_H_CMP(2) PALD_H_CMP(3) PALD_H_ADD(2) PALD_H_ADD(3)
+            "s_mov_b64 exec, %[full]"
+            : PALD_H_ACC(2), PALD_H_ACC(3), PALD_H_MASKS(2), PALD_H_MASKS(3)
+            : [a] "v"(a), [hx] "v"(hx), [full] "s"(full), PALD_H_IN(2), PALD_H_IN(3)
+            : "scc");
     }
-#undef PALD_T4_HEAD_ROT
-#undef PALD_T4_HEAD_WIDE
-#undef PALD_T4_MASKS_ROT
-#undef PALD_T4_MASKS_WIDE
-#undef PALD_T4_OPERANDS
-#undef PALD_T4_INPUTS
 }
+// The same block with the second half weight of each term added to its own
+// accumulators gf (c_xz) and gr (c_zx), so that every accumulator receives at
+// most one addition per y (G = 4).
+__device__ __forceinline__ void cohesion_terms4_split(float (&rf)[4], float (&rr)[4], float (&gf)[4], float (&gr)[4],
+                                                      const uint32_t (&t)[4], uint32_t a, const uint32_t (&b)[4],
+                                                      float hx, const float (&hz)[4], uint64_t full) {
+    uint64_t mi[4], mj[4], mp[4], mq[4];
+    asm(PALD_H_CMP(0) PALD_H_CMP(1) PALD_H_CMP(2) PALD_H_CMP(3)
+        PALD_H_ADD2(0) PALD_H_ADD2(1) PALD_H_ADD2(2) PALD_H_ADD2(3)
+        "s_mov_b64 exec, %[full]"
+        : PALD_H_ACC(0), PALD_H_ACC(1), PALD_H_ACC(2), PALD_H_ACC(3), PALD_H_ACC2(0), PALD_H_ACC2(1), PALD_H_ACC2(2),
+          PALD_H_ACC2(3), PALD_H_MASKS(0), PALD_H_MASKS(1), PALD_H_MASKS(2), PALD_H_MASKS(3)
+        : [a] "v"(a), [hx] "v"(hx), [full] "s"(full), PALD_H_IN(0), PALD_H_IN(1), PALD_H_IN(2), PALD_H_IN(3)
+        : "scc");
+}
+#undef PALD_H_CMP
+#undef PALD_H_ADD
+#undef PALD_H_ADD2
+#undef PALD_H_MASKS
+#undef PALD_H_ACC
+#undef PALD_H_ACC2
+#undef PALD_H_IN
 
 // threadIdx.x, passed through an empty volatile asm: values derived from it
 // are then recomputed where a tile function is called instead of being
@@ -628,10 +588,24 @@ struct P1zStage {
     P1zVec<NC> r[RPW];
 };
 
-// Stage fetch for a stage that reaches past zend (or an unaligned D):
-// bounds-checked loads, +inf outside.  Kept out of line so that the
-// full-stage loads stay plain vector loads.  Row q of this wave is tile row
-// wave + q NW (x rows first, then y rows); lane l loads z = zs + NC l + c.
+// Where a lanes-over-z pass-1 tile finds its rows of D: row x, x in
+// [xlo, xhi), at Dx + (x - xlo) ldx and row y, y in [ylo, yhi), at
+// Dy + (y - ylo) ldy, every row holding all n columns (d_zx = D[x][z] by
+// symmetry).  For the whole matrix Dx = Dy = D, xlo = ylo = 0, xhi = yhi = n;
+// a row panel or a streamed block of rows passes its own buffers.
+struct P1Rows {
+    const float *Dx;
+    int64_t ldx, xlo, xhi;
+    const float *Dy;
+    int64_t ldy, ylo, yhi;
+};
+
+// Stage fetch for a stage that reaches past zend (or unaligned rows), whole
+// matrix: bounds-checked loads, +inf outside.  Kept out of line so that the
+// full-stage loads stay plain vector loads, and with few arguments: a call
+// passes them in vector registers, which count against the kernel's budget.
+// Row q of this wave is tile row wave + q NW (x rows first, then y rows);
+// lane l loads z = zs + NC l + c.
 template <int GX, int GY, int NC>
 __device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetch_edge(
     const float *__restrict__ D, int64_t ldd, int64_t n, int64_t X0, int64_t Y0, int wave, int lane, int64_t zs,
@@ -658,17 +632,52 @@ __device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetc
     return out;
 }
 
-// One lanes-over-z pass-1 tile: pairs x in [X0, X0 + TX), y in [Y0, Y0 + TY),
-// z over [zbeg, zend).  Called by every thread of a workgroup of Cfg::NT
-// threads (tid = thread index); `smw` points to Cfg::LDS_WORDS words of LDS.
-// Writes U (if non-null) and W (if non-null) for the tile's pairs with
-// x <= y and their mirror images, or, in atomic mode, adds the counts into U.
-// Ends with a workgroup barrier, so the LDS can be reused at once.
+// The same for a block of rows (RECT tiles): x row r of the tile (r < xrows
+// exist) at xb + r ldx, y row r (r < yrows) at yb + r ldy.
 template <int GX, int GY, int NC>
-__device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float *__restrict__ D, int64_t n,
-                                            int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
-                                            float *__restrict__ W, int64_t ldw, int64_t X0, int64_t Y0,
-                                            int64_t zbeg, int64_t zend, bool atomic_mode, bool vec_ok) {
+__device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetch_edge_rows(
+    const float *__restrict__ xb, int64_t ldx, int32_t xrows, const float *__restrict__ yb, int64_t ldy, int32_t yrows,
+    int wave, int lane, int64_t zs, int64_t zend, bool vec_ok) {
+    using Cfg = P1zCfg<GX, GY, NC>;
+    P1zStage<Cfg::ROWS_PER_WAVE, NC> out;
+#pragma unroll
+    for (int q = 0; q < Cfg::ROWS_PER_WAVE; ++q) {
+        const int r = wave + q * Cfg::NW;
+        const bool is_x = r < Cfg::TX;
+        const int rr = is_x ? r : r - Cfg::TX;
+        const bool valid = rr < (is_x ? xrows : yrows);
+        const float *base = is_x ? xb + rr * ldx : yb + rr * ldy;
+        const int64_t z0 = zs + (int64_t)NC * lane;
+        if (NC == 4) {
+            const uint4 v = load_raw4(base, 0, 0, z0, valid ? 1 : 0, zend, vec_ok, KEY_INF);
+            out.r[q].v[0] = v.x;
+            out.r[q].v[NC > 1 ? 1 : 0] = v.y;
+            out.r[q].v[NC > 2 ? 2 : 0] = v.z;
+            out.r[q].v[NC > 3 ? 3 : 0] = v.w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                out.r[q].v[c] = (valid && z0 + c < zend) ? __float_as_uint(base[z0 + c]) : KEY_INF;
+        }
+    }
+    return out;
+}
+
+// One lanes-over-z pass-1 tile: pairs x in [X0, X0 + TX), y in [Y0, Y0 + TY),
+// z over [zbeg, zend), rows of D as described by g.  Called by every thread
+// of a workgroup of Cfg::NT threads (tid = thread index); `smw` points to
+// Cfg::LDS_WORDS words of LDS.  Square mode (RECT false, whole matrix): writes
+// U (if non-null) and W (if non-null) for the tile's pairs with x <= y and
+// their mirror images, or, in atomic mode, adds the counts into U.  RECT
+// (a block of rows x): writes every pair x < xhi, y < yhi of the tile, U at
+// U[(x - xlo) ldu + y] and the weight transposed, W[y ldw + (x - xlo)]; no
+// atomic mode.  Ends with a workgroup barrier, so the LDS can be reused at
+// once.
+template <int GX, int GY, int NC, bool RECT = false>
+__device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Rows g, int64_t n,
+                                              int32_t *__restrict__ U, int64_t ldu, float *__restrict__ W,
+                                              int64_t ldw, int64_t X0, int64_t Y0, int64_t zbeg, int64_t zend,
+                                              bool atomic_mode, bool vec_ok) {
     using Cfg = P1zCfg<GX, GY, NC>;
     constexpr int RPW = Cfg::ROWS_PER_WAVE;
     const int lane = tid & 63;
@@ -695,8 +704,8 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     {
         uint32_t *kw = smw + Cfg::ROWS * Cfg::ZS + wave * (Cfg::WX * Cfg::WY);
         if (lane < Cfg::WX * Cfg::WY) {
-            const int64_t x = min(xw + lane / Cfg::WY, n - 1), y = min(yw + lane % Cfg::WY, n - 1);
-            kw[lane] = __float_as_uint(D[x * ldd + y]);
+            const int64_t x = min(xw + lane / Cfg::WY, g.xhi - 1), y = min(yw + lane % Cfg::WY, n - 1);
+            kw[lane] = __float_as_uint(g.Dx[(x - g.xlo) * g.ldx + y]);
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -711,17 +720,18 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     // from fixed row pointers and one 32-bit offset, without checks (vector
     // loads when the rows are 16-byte aligned, else one load per value); the
     // others go through the bounds-checked p1z_fetch_edge().
-    const bool rows_in = X0 + Cfg::TX <= n && Y0 + Cfg::TY <= n;
+    const bool rows_in = X0 + Cfg::TX <= g.xhi && Y0 + Cfg::TY <= g.yhi;
     const int32_t nst_fast = rows_in ? (int32_t)((zend - zbeg) / Cfg::ZS) : 0;  // leading stages needing no checks
     const char *rowp[RPW];
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
         const int r = wave + q * Cfg::NW;
-        const int64_t row = r < Cfg::TX ? X0 + r : Y0 + (r - Cfg::TX);
+        const bool is_x = r < Cfg::TX;
+        const int64_t rel = is_x ? min(X0 + r, g.xhi - 1) - g.xlo : min(Y0 + (r - Cfg::TX), g.yhi - 1) - g.ylo;
         // (the byte offset made explicitly wave-uniform, so that the row
         // pointers stay in scalar registers)
-        const uint64_t ro = (uint64_t)(min(row, n - 1) * ldd + zbeg) * sizeof(float);
-        rowp[q] = reinterpret_cast<const char *>(D) +
+        const uint64_t ro = (uint64_t)(rel * (is_x ? g.ldx : g.ldy) + zbeg) * sizeof(float);
+        rowp[q] = reinterpret_cast<const char *>(is_x ? g.Dx : g.Dy) +
                   (((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(ro >> 32)) << 32) |
                    (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)ro));
     }
@@ -758,8 +768,14 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
             if (st < nst_fast)
                 fetch_fast((uint32_t)st * STAGE_BYTES + lane_off);
             else
-                pre = p1z_fetch_edge<GX, GY, NC>(D, ldd, n, X0, Y0, wave, lane, zbeg + (int64_t)st * Cfg::ZS, zend,
-                                                 VEC);
+                if constexpr (RECT)
+                    pre = p1z_fetch_edge_rows<GX, GY, NC>(
+                        g.Dx + (X0 - g.xlo) * g.ldx, g.ldx, (int32_t)min((int64_t)Cfg::TX, g.xhi - X0),
+                        g.Dy + (Y0 - g.ylo) * g.ldy, g.ldy, (int32_t)min((int64_t)Cfg::TY, g.yhi - Y0), wave, lane,
+                        zbeg + (int64_t)st * Cfg::ZS, zend, VEC);
+                else  // whole matrix: g.Dx = g.Dy, rows [0, n)
+                    pre = p1z_fetch_edge<GX, GY, NC>(g.Dx, g.ldx, n, X0, Y0, wave, lane,
+                                                     zbeg + (int64_t)st * Cfg::ZS, zend, VEC);
         };
         // LDS layout of a stage: [row][c][lane], element = z zs + NC lane + c,
         // so that the reads of one component c are contiguous over the lanes
@@ -834,6 +850,12 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
     for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) mine = lane == p ? cnt[p] : mine;
     if (lane >= Cfg::WX * Cfg::WY) return;
     const int64_t x = xw + lane / Cfg::WY, y = yw + lane % Cfg::WY;
+    if constexpr (RECT) {
+        if (x >= g.xhi || y >= g.yhi) return;
+        if (U) U[(x - g.xlo) * ldu + y] = mine;
+        if (W) W[y * ldw + (x - g.xlo)] = x != y ? weight_of(mine) : 0.0f;
+        return;
+    }
     if (x >= n || y >= n || x > y) return;
     const bool mirror = x != y;
     if (atomic_mode) {
@@ -850,6 +872,16 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
         W[x * ldw + y] = w;
         if (mirror) W[y * ldw + x] = w;
     }
+}
+
+// The whole-matrix form of pass1z_tile_g (square mode).
+template <int GX, int GY, int NC>
+__device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float *__restrict__ D, int64_t n,
+                                            int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
+                                            float *__restrict__ W, int64_t ldw, int64_t X0, int64_t Y0,
+                                            int64_t zbeg, int64_t zend, bool atomic_mode, bool vec_ok) {
+    pass1z_tile_g<GX, GY, NC, false>(tid, smw, P1Rows{D, ldd, 0, n, D, ldd, 0, n}, n, U, ldu, W, ldw, X0, Y0, zbeg,
+                                     zend, atomic_mode, vec_ok);
 }
 
 // The single-matrix pass-1 kernel: 4 x 2 waves (16 x 16 pairs, 512 threads),
@@ -871,8 +903,11 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 #ifndef PALD_P1Z_NC
 #define PALD_P1Z_NC 2
 #endif
+// 6 waves per SIMD (3 workgroups per CU) is what the tile is built for; the
+// bound keeps a code change from quietly taking the kernel past 80 VGPRs and
+// down to 2 workgroups per CU (83 VGPRs: 162 instead of 132 ms at n = 16384)
 #ifndef PALD_P1Z_MIN_WAVES
-#define PALD_P1Z_MIN_WAVES 1
+#define PALD_P1Z_MIN_WAVES 6
 #endif
 using P1zMain = P1zCfg<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>;
 constexpr int P1Z_TX = P1zMain::TX, P1Z_TY = P1zMain::TY, P1Z_NT = P1zMain::NT, P1Z_ZS = P1zMain::ZS;
@@ -936,19 +971,21 @@ __global__ void zero_i32_kernel(int32_t *__restrict__ P, int64_t ld, int64_t n) 
 // C = fl32(sum / (n-1)); otherwise it writes float64 partial sums
 // partial[chunk][x][z] (ld n) for finalize_kernel.
 //
-// Per y the tile stages row y of D and of W restricted to the x range and to
-// the z range (a = d_yx, b = d_yz, W_yx, W_yz; D and W are symmetric), and
-// the halves W/2 computed once while staging.  Rows
-// y >= n, and rows past the chunk, stage W = 0 and so add nothing; the terms
-// y = x and y = z add nothing because W_xx = W_zz = 0.
+// Per y the tile stages row y of D and the halves of row y of W, restricted
+// to the x range and to the z range (a = d_yx, b = d_yz, W_yx / 2, W_yz / 2;
+// D and W are symmetric; halving is exact).  Rows y >= n, and rows past the
+// chunk, stage W = 0 and so add nothing; the terms y = x and y = z add
+// nothing because W_xx = W_zz = 0.
 //
-// The compare results are combined as 64-lane masks with scalar instructions
-// (s_and), so no vector select waits on a mask written by the vector
-// instruction just before it.
-
-#ifndef PALD_P2_RUN
-#define PALD_P2_RUN 12
-#endif
+// Each term is added as one or two exact half weights (cohesion_terms4).
+// Float32 runs: in the single-accumulator form a run covers P2_RUN = 6 values
+// of y, so it holds at most 12 additions and the relative error of a C entry
+// stays below (12 + 3) 2^-24 = 8.9e-7 (the run, the Kahan fold, the rounding
+// of W and the final store).  In the split form the second half weight of a
+// term goes to accumulators of its own that join the run at each fold: runs
+// of P2_RUN_SPLIT = 12 values of y, at most 12 additions per accumulator plus
+// the join, below (11 + 1 + 2 + 1 + 1) 2^-24 = 9.5e-7.
+constexpr int P2_RUN = 6, P2_RUN_SPLIT = 12;
 // minimum waves per SIMD the pass-2 kernel is compiled for (its VGPR budget)
 #ifndef PALD_P2_MIN_WAVES
 #define PALD_P2_MIN_WAVES 3
@@ -960,13 +997,12 @@ struct Pass2Cfg {
     static constexpr int TZ = T / RZ;                   // threads along z
     static constexpr int NT = TX * TZ;
     static constexpr int ROW = 4 * T;                   // loaded per y: a | W_yx | b | W_yz
-    static constexpr int LDS_ROW = 6 * T;               // staged per y: ... | W_yx/2 | W_yz/2
+    static constexpr int LDS_ROW = 4 * T;               // staged per y: a | W_yx/2 | b | W_yz/2
     static constexpr int VEC_PER_CHUNK = KY * ROW / 4;
     static constexpr int VEC_PER_THREAD = (VEC_PER_CHUNK + NT - 1) / NT;  // the last round may be partial
     static constexpr bool VEC_EVEN = VEC_PER_CHUNK % NT == 0;
     static constexpr int LDS_VEC = 2 * KY * LDS_ROW / 4; // uint4 of LDS, double-buffered
-    static constexpr int RUN = PALD_P2_RUN;             // float32 run length before a Kahan fold
-    static_assert(KY % RUN == 0, "KY must be a multiple of the run length");
+    static_assert(KY % P2_RUN == 0 && KY % P2_RUN_SPLIT == 0, "KY must be a multiple of the run lengths");
     static_assert(T % 4 == 0, "tile side must be a multiple of 4");
 };
 
@@ -983,9 +1019,11 @@ struct Pass2Out {
 };
 
 // One pass-2 tile (bx, bz), bx <= bz, over the y range [ybeg, yend).  Called
-// by every thread of a workgroup of Pass2Cfg::NT threads; `sm` points to
-// Pass2Cfg::LDS_VEC uint4 of LDS.
-template <int T, int RX, int KY, bool F64, bool FEW_SGPR = false>
+// by every thread of a workgroup of Pass2Cfg::NT threads, all lanes active;
+// `sm` points to Pass2Cfg::LDS_VEC uint4 of LDS.  FEW_SGPR: compare blocks of
+// two pairs instead of four (fewer scalar registers).  SPLIT: the split-run
+// form (16 more accumulator VGPRs for 2 x 4 pairs, runs twice as long).
+template <int T, int RX, int KY, bool F64, bool FEW_SGPR = false, bool SPLIT = false>
 __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__restrict__ D, int64_t n, int64_t ldd,
                                            const float *__restrict__ W, int64_t ldw, Pass2Out out, int32_t bx,
                                            int32_t bz, int64_t ybeg, int64_t yend, bool vec_ok_d, bool vec_ok_w) {
@@ -1011,7 +1049,10 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
     // previous fold, so r holds (run sum - c) when the run ends -- the
     // compensated summand of Kahan's algorithm -- and no separate compensation
     // register stays live during a run.
+    // In the split form the second half weight of a term goes to gf / gr,
+    // which join the run at the fold.
     float sf[RX][RZ], rf[RX][RZ], sr[RX][RZ], rr[RX][RZ];
+    float gf[RX][RZ], gr[RX][RZ];
     double af[RX][RZ], ar[RX][RZ];
 #pragma unroll
     for (int i = 0; i < RX; ++i)
@@ -1019,6 +1060,7 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
         for (int j = 0; j < RZ; ++j) {
             sf[i][j] = rf[i][j] = 0.0f;
             sr[i][j] = rr[i][j] = 0.0f;
+            gf[i][j] = gr[i][j] = 0.0f;
             af[i][j] = ar[i][j] = 0.0;
         }
 
@@ -1048,13 +1090,11 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
             const int g = v % (Cfg::ROW / 4);
             const int seg = g / (T / 4);
             uint4 *row = sm + buf * (Cfg::LDS_VEC / 2) + r * (Cfg::LDS_ROW / 4);
-            row[g] = pre[k];
-            if (seg == 1 || seg == 3) {  // W segment: also its halves, once per staged value
-                const uint4 w = pre[k];
-                row[T + (seg == 1 ? 0 : T / 4) + g % (T / 4)] =
-                    make_uint4(__float_as_uint(0.5f * __uint_as_float(w.x)), __float_as_uint(0.5f * __uint_as_float(w.y)),
+            uint4 w = pre[k];
+            if (seg == 1 || seg == 3)  // W segment: staged as its halves (exact)
+                w = make_uint4(__float_as_uint(0.5f * __uint_as_float(w.x)), __float_as_uint(0.5f * __uint_as_float(w.y)),
                                __float_as_uint(0.5f * __uint_as_float(w.z)), __float_as_uint(0.5f * __uint_as_float(w.w)));
-            }
+            row[g] = w;
         }
     };
 
@@ -1070,30 +1110,27 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
         const int buf = (int)(c & 1);
         if (c + 1 < nchunks) fetch(ybeg + (c + 1) * KY);
         const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (Cfg::LDS_VEC / 2));
-        // operands of staged row yr: a = d_yx, W_yx, W_yx/2 over x; b = d_yz, W_yz, W_yz/2 over z
-        auto load_row = [&](int yr, uint32_t (&av)[RX], float (&wx)[RX], float (&whx)[RX], uint32_t (&bv)[RZ],
-                            float (&wz)[RZ], float (&whz)[RZ]) {
+        // operands of staged row yr: a = d_yx, W_yx/2 over x; b = d_yz, W_yz/2 over z
+        auto load_row = [&](int yr, uint32_t (&av)[RX], float (&whx)[RX], uint32_t (&bv)[RZ], float (&whz)[RZ]) {
             const uint32_t *row = s + yr * Cfg::LDS_ROW;
 #pragma unroll
             for (int i = 0; i < RX; ++i) {
                 av[i] = row[tx * RX + i];
-                wx[i] = __uint_as_float(row[T + tx * RX + i]);
-                whx[i] = __uint_as_float(row[4 * T + tx * RX + i]);
+                whx[i] = __uint_as_float(row[T + tx * RX + i]);
             }
 #pragma unroll
             for (int j = 0; j < RZ; ++j) {
                 bv[j] = row[2 * T + tz * RZ + j];
-                wz[j] = __uint_as_float(row[3 * T + tz * RZ + j]);
-                whz[j] = __uint_as_float(row[5 * T + tz * RZ + j]);
+                whz[j] = __uint_as_float(row[3 * T + tz * RZ + j]);
             }
         };
         if (F64) {
-            // reference form: plain float64 accumulation, no runs
+            // reference form: plain float64 accumulation of W or W/2, no runs
 #pragma unroll 2
             for (int yr = 0; yr < KY; ++yr) {
                 uint32_t av[RX], bv[RZ];
-                float wx[RX], whx[RX], wz[RZ], whz[RZ];
-                load_row(yr, av, wx, whx, bv, wz, whz);
+                float whx[RX], whz[RZ];
+                load_row(yr, av, whx, bv, whz);
 #pragma unroll
                 for (int i = 0; i < RX; ++i)
 #pragma unroll
@@ -1101,24 +1138,32 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
                         const uint32_t tt = t[i][j];
                         const uint64_t in = lane_mask(tt <= av[i]) & lane_mask(tt <= bv[j]);
                         float vf = lane_bit(in) ? whx[i] : 0.0f;
-                        vf = lane_bit(in & lane_mask(tt < bv[j])) ? wx[i] : vf;
+                        vf = lane_bit(in & lane_mask(tt < bv[j])) ? whx[i] + whx[i] : vf;
                         float vr = lane_bit(in) ? whz[j] : 0.0f;
-                        vr = lane_bit(in & lane_mask(tt < av[i])) ? wz[j] : vr;
+                        vr = lane_bit(in & lane_mask(tt < av[i])) ? whz[j] + whz[j] : vr;
                         af[i][j] += (double)vf;
                         ar[i][j] += (double)vr;
                     }
             }
         } else {
-#pragma unroll 1
-            for (int y0 = 0; y0 < KY; y0 += Cfg::RUN) {
+            const uint64_t full = __builtin_amdgcn_read_exec();
+            constexpr int RUN = SPLIT ? P2_RUN_SPLIT : P2_RUN;
+            // (the runs of a stage fully unrolled: no register copies of the
+            // Kahan state between runs)
 #pragma unroll
-                for (int yy = 0; yy < Cfg::RUN; ++yy) {
+            for (int y0 = 0; y0 < KY; y0 += RUN) {
+#pragma unroll
+                for (int yy = 0; yy < RUN; ++yy) {
                     uint32_t av[RX], bv[RZ];
-                    float wx[RX], whx[RX], wz[RZ], whz[RZ];
-                    load_row(y0 + yy, av, wx, whx, bv, wz, whz);
+                    float whx[RX], whz[RZ];
+                    load_row(y0 + yy, av, whx, bv, whz);
 #pragma unroll
-                    for (int i = 0; i < RX; ++i)
-                        cohesion_terms4<FEW_SGPR>(rf[i], rr[i], t[i], av[i], bv, wx[i], whx[i], wz, whz);
+                    for (int i = 0; i < RX; ++i) {
+                        if constexpr (SPLIT)
+                            cohesion_terms4_split(rf[i], rr[i], gf[i], gr[i], t[i], av[i], bv, whx[i], whz, full);
+                        else
+                            cohesion_terms4<FEW_SGPR ? 2 : 4>(rf[i], rr[i], t[i], av[i], bv, whx[i], whz, full);
+                    }
                 }
                 // Kahan fold of the finished runs (r = run - c): s + r, with the
                 // new negated compensation -c = r - ((s + r) - s) left in r.
@@ -1126,6 +1171,11 @@ __device__ __forceinline__ void pass2_tile(int tid, uint4 *sm, const float *__re
                 for (int i = 0; i < RX; ++i)
 #pragma unroll
                     for (int j = 0; j < RZ; ++j) {
+                        if constexpr (SPLIT) {  // the second halves join the run first
+                            rf[i][j] += gf[i][j];
+                            rr[i][j] += gr[i][j];
+                            gf[i][j] = gr[i][j] = 0.0f;
+                        }
                         float tk = sf[i][j] + rf[i][j];
                         rf[i][j] = rf[i][j] - (tk - sf[i][j]);
                         sf[i][j] = tk;
@@ -1185,7 +1235,8 @@ __global__ __launch_bounds__((Pass2Cfg<T, RX, KY>::NT), PALD_P2_MIN_WAVES) void 
     } else {
         out.slab = partial + (int64_t)blockIdx.y * n * n;
     }
-    pass2_tile<T, RX, KY, F64>((int)threadIdx.x, sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend, vec_ok_d != 0, vec_ok_w != 0);
+    pass2_tile<T, RX, KY, F64, false, true>((int)threadIdx.x, sm, D, n, ldd, W, ldw, out, bx, bz, ybeg, yend,
+                                           vec_ok_d != 0, vec_ok_w != 0);
 }
 
 // C_xz = fl32( sum_k partial[k][x][z] / (n-1) ), the only cross-tile reduction.

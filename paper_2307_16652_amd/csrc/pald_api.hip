@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -15,6 +16,7 @@
 #include "host_common.hpp"
 #include "pairwise.hpp"
 #include "batched.hpp"
+#include "rows.hpp"
 #include "triplet.hpp"
 #include "tuned_gfx950.h"
 
@@ -40,14 +42,19 @@ constexpr bool P1_LANES_Z = PALD_P1_LANES_Z != 0;
 // z granularity of a pass-1 chunk: one stage of whichever kernel runs
 constexpr int P1_ZQ = P1_LANES_Z ? P1Z_ZS : P1_KZ;
 // pass 2: symmetric 64 x 64 (x,z) tiles, P2_RX x 4 pairs (both directions) per thread,
-// 16 y rows per stage
+// P2_KY y rows per stage.  2 x 4 pairs (512 threads, about 100 VGPRs: 5 waves per
+// SIMD) against 4 x 4 (256 threads, 168 VGPRs: 3 waves): n = 16384 pass 2 in
+// 442 against 498 ms -- the compares of one wave issue beside the float32
+// additions of another, which needs more waves per SIMD than the larger
+// register tile leaves.
 #ifndef PALD_P2_RX
-#define PALD_P2_RX 4
+#define PALD_P2_RX 2
 #endif
-#ifndef PALD_P2_KY
-#define PALD_P2_KY 12
+// 24 y rows per LDS stage (two split runs): 429 against 443 ms with 12
+#ifndef PALD_P2_SINGLE_KY
+#define PALD_P2_SINGLE_KY 24
 #endif
-constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = PALD_P2_KY;
+constexpr int P2_T = 64, P2_RX = PALD_P2_RX, P2_KY = PALD_P2_SINGLE_KY;
 using P2 = Pass2Cfg<P2_T, P2_RX, P2_KY>;
 
 constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
@@ -274,7 +281,7 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 5, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0, (int32_t)t0);
+        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0, (int32_t)t0, 1.0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     // the upper triangle holds U; mirror it
@@ -291,7 +298,8 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     if (ws_bytes < t.bytes) return PALD_ERR_ARG;
     char *base = static_cast<char *>(ws);
     float *W = reinterpret_cast<float *>(base + t.off_w);
-    double *A = reinterpret_cast<double *>(base + t.off_a);
+    unsigned long long *A = reinterpret_cast<unsigned long long *>(base + t.off_a);
+    const double scale = std::ldexp(1.0, triplet_fixed_bits(n));
     int32_t *Ub = U;
     int64_t ldub = ldu;
     if (!Ub) {
@@ -302,17 +310,17 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
     weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, t.ldw, n);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
-    triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A);
+    triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A, scale);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 6, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1, (int32_t)t0);
+        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1, (int32_t)t0, scale);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     ScopedTiming tm(timing, 7, s);
-    triplet_finalize_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(A, n, C, ldc);
+    triplet_finalize_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(A, n, C, ldc, 1.0 / scale);
     return launch_status();
 }
 
@@ -344,7 +352,75 @@ pald_status run_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int
 
 }  // namespace
 
-// ---- fixed workspace of pald_cohesion_noalloc -------------------------------
+// ---- blocks of rows ------------------------------------------------------------
+constexpr int64_t ROWS_P1_TILES_PER_LAUNCH = 1 << 20;
+static_assert(ROWS_P1_TILES_PER_LAUNCH * P1Z_NT < MAX_X_ITEMS, "launch pieces must hold fewer than 2^32 work-items");
+
+// Row-block options: the pairwise variant, compensated accumulation, no forced splits.
+pald_status rows_opts(const Opts &o) {
+    if ((o.variant != PALD_VARIANT_AUTO && o.variant != PALD_VARIANT_PAIRWISE) || o.accum != PALD_ACC_COMPENSATED ||
+        o.y_chunks != 0 || o.z_chunks != 0)
+        return PALD_ERR_UNSUPPORTED;
+    return PALD_OK;
+}
+
+inline int64_t rows_ldwt(int64_t rows) { return (int64_t)align_up((size_t)rows, 64); }
+
+// Pass 1 of the pairs (x, y), x in [g.xlo, g.xhi), y in [g.ylo, g.yhi): U
+// (may be null) and the transposed weights Wt.
+pald_status rows_pass1(const P1Rows &g, int64_t n, int32_t *U, int64_t ldu, float *Wt, int64_t ldwt, bool vec,
+                       hipStream_t s, bool timing) {
+    const int64_t tiles = ceil_div(g.xhi - g.xlo, P1Z_TX) * ceil_div(g.yhi - g.ylo, P1Z_TY);
+    for (int64_t t0 = 0; t0 < tiles; t0 += ROWS_P1_TILES_PER_LAUNCH) {
+        ScopedTiming tm(timing, 13, s);
+        const unsigned gx = (unsigned)std::min<int64_t>(ROWS_P1_TILES_PER_LAUNCH, tiles - t0);
+        pass1_rows_kernel<<<gx, P1Z_NT, 0, s>>>(g, n, U, ldu, Wt, ldwt, vec ? 1 : 0, t0);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
+    return PALD_OK;
+}
+
+// Pass 2 of the rows [g.xlo, g.xhi) over y in [g.ylo, g.yhi): C, or added into acc.
+pald_status rows_pass2(const P1Rows &g, int64_t n, const float *Wt, int64_t ldwt, float *C, int64_t ldc, double *acc,
+                       int64_t ldacc, bool vec_d, hipStream_t s, bool timing) {
+    const int64_t xt = ceil_div(g.xhi - g.xlo, P2R_T), zt = ceil_div(n, P2R_T);
+    if (xt > 65535 || zt > INT32_MAX) return PALD_ERR_UNSUPPORTED;
+    ScopedTiming tm(timing, 14, s);
+    pass2_rows_kernel<<<dim3((unsigned)zt, (unsigned)xt), P2R_NT, 0, s>>>(g, n, Wt, ldwt, C, ldc, acc, ldacc, g.ylo,
+                                                                            g.yhi, vec_d ? 1 : 0, 1);
+    return launch_status();
+}
+
+// Device workspace of the out-of-core mode for panels of P rows: the panel's
+// rows of D, one block of P rows of D, the transposed weights (n x ldwt), the
+// panel's U, its float64 accumulators and its C.
+struct OocLayout {
+    int64_t P = 0, ldp = 0, ldwt = 0;
+    size_t off_dp = 0, off_db = 0, off_wt = 0, off_u = 0, off_acc = 0, off_c = 0, bytes = 0;
+};
+
+OocLayout ooc_layout(int64_t n, int64_t P) {
+    OocLayout L;
+    L.P = P;
+    L.ldp = (int64_t)align_up((size_t)n, 64);
+    L.ldwt = rows_ldwt(P);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, ALIGN);
+        return at;
+    };
+    L.off_dp = take((size_t)P * L.ldp * sizeof(float));
+    L.off_db = take((size_t)P * L.ldp * sizeof(float));
+    L.off_wt = take((size_t)n * L.ldwt * sizeof(float));
+    L.off_u = take((size_t)P * n * sizeof(int32_t));
+    L.off_acc = take((size_t)P * n * sizeof(double));
+    L.off_c = take((size_t)P * n * sizeof(float));
+    L.bytes = off;
+    return L;
+}
+
+// ---- fixed workspace of pald_cohesion_noalloc// ---- fixed workspace of pald_cohesion_noalloc -------------------------------
 // One array per GPU, held until the process ends.  Host code never passes the
 // array's name to a kernel (on the host it is only a stand-in for the symbol):
 // noalloc_scratch() looks up its device address once per device and every use
@@ -453,6 +529,107 @@ pald_status pald_cohesion_noalloc(const float *D, int64_t n, int64_t ldd, int32_
     char *base = nullptr;
     if (pald_status st = noalloc_scratch(&base); st != PALD_OK) return st;
     return run_cohesion(D, n, ldd, U, ldu, C, ldc, base, p, o, (hipStream_t)stream);
+}
+
+size_t pald_rows_workspace_bytes(int64_t n, int64_t rows, const pald_options *opt) {
+    Opts o;
+    if (n < 2 || rows < 1 || rows > n || read_opts(opt, o) != PALD_OK || rows_opts(o) != PALD_OK) return 0;
+    return std::max<size_t>(align_up((size_t)n * rows_ldwt(rows) * sizeof(float), ALIGN), ALIGN);
+}
+
+pald_status pald_cohesion_rows(const float *D, int64_t n, int64_t ldd, int64_t x0, int64_t x1, int32_t *U, int64_t ldu,
+                               float *C, int64_t ldc, void *ws, size_t ws_bytes, void *stream, const pald_options *opt) {
+    Opts o;
+    if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
+    if (pald_status st = rows_opts(o); st != PALD_OK) return st;
+    if (!D || !C || !ws || n < 2 || ldd < n || ldc < n || (U && ldu < n) || x0 < 0 || x1 <= x0 || x1 > n)
+        return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0 || ws_bytes < pald_rows_workspace_bytes(n, x1 - x0, opt))
+        return PALD_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
+    float *Wt = static_cast<float *>(ws);
+    const int64_t ldwt = rows_ldwt(x1 - x0);
+    const bool vec = aligned16(D) && ldd % 4 == 0;
+    const P1Rows g{D + x0 * ldd, ldd, x0, x1, D, ldd, 0, n};
+    if (pald_status st = rows_pass1(g, n, U, ldu, Wt, ldwt, vec, s, timing); st != PALD_OK) return st;
+    return rows_pass2(g, n, Wt, ldwt, C, ldc, nullptr, 0, vec && x0 % 4 == 0, s, timing);
+}
+
+size_t pald_ooc_workspace_bytes(int64_t n, int64_t panel_rows) {
+    if (n < 2 || panel_rows < 1) return 0;
+    return ooc_layout(n, std::min(panel_rows, n)).bytes;
+}
+
+pald_status pald_cohesion_ooc(const float *D_host, int64_t n, int64_t ldd, int32_t *U_host, int64_t ldu, float *C_host,
+                              int64_t ldc, void *ws, size_t ws_bytes, void *stream, const pald_options *opt) {
+    Opts o;
+    if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
+    if (pald_status st = rows_opts(o); st != PALD_OK) return st;
+    if (!D_host || !C_host || !ws || n < 2 || ldd < n || ldc < n || (U_host && ldu < n)) return PALD_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
+    // the tallest panel (a multiple of 16 rows, at most n) whose layout fits
+    int64_t P = 0;
+    for (int64_t lo = 1, hi = ceil_div(n, 16); lo <= hi;) {
+        const int64_t mid = (lo + hi) / 2;
+        if (ooc_layout(n, std::min(16 * mid, n)).bytes <= ws_bytes) {
+            P = std::min(16 * mid, n);
+            lo = mid + 1;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    if (P == 0) return PALD_ERR_ARG;
+    const OocLayout L = ooc_layout(n, P);
+    char *base = static_cast<char *>(ws);
+    float *Dp = reinterpret_cast<float *>(base + L.off_dp), *Db = reinterpret_cast<float *>(base + L.off_db);
+    float *Wt = reinterpret_cast<float *>(base + L.off_wt), *Cp = reinterpret_cast<float *>(base + L.off_c);
+    int32_t *Up = reinterpret_cast<int32_t *>(base + L.off_u);
+    double *acc = reinterpret_cast<double *>(base + L.off_acc);
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
+    const size_t row_bytes = (size_t)n * sizeof(float), ldp_bytes = (size_t)L.ldp * sizeof(float);
+    auto rows_to_device = [&](float *dst, int64_t r0, int64_t r1) {
+        ScopedTiming tm(timing, 15, s);
+        return hipMemcpy2DAsync(dst, ldp_bytes, D_host + r0 * ldd, (size_t)ldd * sizeof(float), row_bytes,
+                                (size_t)(r1 - r0), hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    for (int64_t x0 = 0; x0 < n; x0 += P) {
+        const int64_t x1 = std::min(n, x0 + P), rows = x1 - x0;
+        if (!rows_to_device(Dp, x0, x1)) return PALD_ERR_DEVICE;
+        // pass 1, one block of y rows at a time
+        for (int64_t y0 = 0; y0 < n; y0 += P) {
+            const int64_t y1 = std::min(n, y0 + P);
+            if (!rows_to_device(Db, y0, y1)) return PALD_ERR_DEVICE;
+            const P1Rows g{Dp, L.ldp, x0, x1, Db, L.ldp, y0, y1};
+            if (pald_status st = rows_pass1(g, n, Up, n, Wt, L.ldwt, true, s, timing); st != PALD_OK) return st;
+        }
+        // pass 2 into float64 accumulators, then C
+        const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
+        zero_f64_kernel<<<dim3(gx, rows_grid(rows)), 256, 0, s>>>(acc, n, rows, n);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+        for (int64_t y0 = 0; y0 < n; y0 += P) {
+            const int64_t y1 = std::min(n, y0 + P);
+            if (!rows_to_device(Db, y0, y1)) return PALD_ERR_DEVICE;
+            const P1Rows g{Dp, L.ldp, x0, x1, Db, L.ldp, y0, y1};
+            if (pald_status st = rows_pass2(g, n, Wt, L.ldwt, nullptr, 0, acc, n, true, s, timing); st != PALD_OK)
+                return st;
+        }
+        {
+            ScopedTiming tm(timing, 14, s);
+            rows_finalize_kernel<<<dim3(gx, rows_grid(rows)), 256, 0, s>>>(acc, n, rows, n, Cp, n);
+            if (pald_status st = launch_status(); st != PALD_OK) return st;
+        }
+        ScopedTiming tm(timing, 15, s);
+        if (hipMemcpy2DAsync(C_host + x0 * ldc, (size_t)ldc * sizeof(float), Cp, row_bytes, row_bytes, (size_t)rows,
+                             hipMemcpyDeviceToHost, s) != hipSuccess)
+            return PALD_ERR_DEVICE;
+        if (U_host && hipMemcpy2DAsync(U_host + x0 * ldu, (size_t)ldu * sizeof(int32_t), Up, (size_t)n * sizeof(int32_t),
+                                       (size_t)n * sizeof(int32_t), (size_t)rows, hipMemcpyDeviceToHost,
+                                       s) != hipSuccess)
+            return PALD_ERR_DEVICE;
+    }
+    return hipStreamSynchronize(s) == hipSuccess ? PALD_OK : PALD_ERR_DEVICE;
 }
 
 pald_status pald_check_input(const float *D, int64_t n, int64_t ldd, void *ws, size_t ws_bytes, void *stream,
@@ -660,6 +837,15 @@ int32_t resident_per_cu() {
     return per;
 }
 
+int32_t lean_resident_per_cu() {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2_lean_kernel, BATCH_LEAN_THREADS, 0) !=
+            hipSuccess ||
+        per < 1)
+        per = 1;
+    return per;
+}
+
 }  // namespace
 
 struct pald_batch_plan {
@@ -705,7 +891,7 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
             if (pald_status st = launch_status(); st != PALD_OK) return st;
         }
     if (plan->lean2) {
-        batched_pass2_lean_kernel<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
+        batched_pass2_lean_kernel<<<(unsigned)plan->grid, BATCH_LEAN_THREADS, 0, s>>>(
             plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, C, Wr, ctr, stamps, aligned16(D) ? 1 : 0);
         return launch_status();
     }
@@ -746,6 +932,9 @@ pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const p
     }
     p->lean2 = PALD_BATCH_LEAN_PASS2 && !p->L.tiles1z.empty();
     for (const BatchMatrix &m : p->L.mats) p->lean2 = p->lean2 && m.y_chunks == 1 && m.tile2 == BATCH_P2_T;
+    // the lean kernel's own resident capacity (a split-mode queue does not depend on the grid)
+    if (p->lean2 && !(cfg && cfg->workgroups_per_cu > 0) && pald_tuned::kBatchWorkgroupsPerCu <= 0)
+        p->grid = cus * lean_resident_per_cu();
     size_t off = 0;
     p->off_w = off;
     off = align_up(off + (size_t)p->L.w_floats * sizeof(float), ALIGN);

@@ -25,11 +25,16 @@
 // shuffles), and added to the float64 accumulator with one atomic per value;
 // the (q, r) terms are summed over the wave's p with shuffles, then over the
 // four waves through LDS.  Every pair's terms come from several owners, so the
-// global sums use float64 atomics (C) and int32 atomics on the upper triangle
-// of U (mirrored to the lower one after the pass): U stays exact;
-// C is accurate to the same bound as the pairwise path but its last float64
-// bits depend on the order of the atomic adds, so it is not bitwise
-// reproducible run to run.
+// global sums use integer atomics, which commute: int32 on the upper triangle
+// of U (mirrored to the lower one after the pass) and, for C, 64-bit
+// fixed-point accumulators A with F = 61 - ceil(log2 n) fraction bits.  Each
+// owner's float32 partial sum is a multiple of its last mantissa bit, at
+// least 2^-(ceil(log2 n) + 24) (every term is W_xy or W_xy / 2 with
+// W_xy >= 1/n), so for n <= 2^18 it converts to fixed point exactly, and
+// every sum stays below n/2, so below 2^60 in fixed point.  The result is
+// the exact sum of the owners' partials whatever order the atomics land in:
+// C is bitwise reproducible, and accurate to the same bound as the pairwise
+// path.
 //
 // On a GPU this variant does fewer comparisons than the pairwise one but
 // moves O(n^3 / 64) partial sums through atomics, where the pairwise tiles
@@ -72,12 +77,23 @@ __global__ void triplet_init_u_kernel(const float *__restrict__ D, int64_t n, in
     }
 }
 
-// The terms whose third point is one of the pair, into the float64 accumulator A:
+// Fixed point of the C accumulators: value v is stored as v 2^F in 64 bits.
+__host__ __device__ inline int32_t triplet_fixed_bits(int64_t n) {
+    int32_t lg = 0;
+    while (((int64_t)1 << lg) < n) ++lg;
+    return 61 - lg;
+}
+__device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
+    return (unsigned long long)__double2ll_rn(v * scale);
+}
+
+// The terms whose third point is one of the pair, into the fixed-point accumulator A:
 //   A_xx = sum_{y != x} s(0, d_xy) W_xy       (third point x in the focus of (x, y))
 //   A_xy = s(d_xy, 0) W_xy, x != y            (third point y; nonzero only if d_xy = 0)
-// with s(p, q) = [p < q] + 1/2 [p == q].
+// with s(p, q) = [p < q] + 1/2 [p == q]; the diagonal sum runs in float64 in a
+// fixed order (tree over the workgroup) and is converted once.
 __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W,
-                                      int64_t ldw, double *__restrict__ A) {
+                                      int64_t ldw, unsigned long long *__restrict__ A, double scale) {
     __shared__ double red[256];
     for (int64_t x = blockIdx.x; x < n; x += gridDim.x) {
         double diag = 0.0;
@@ -86,7 +102,7 @@ __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, in
             const bool zero = key_of(D[x * ldd + y]) == 0u;
             const float w = W[x * ldw + y];
             diag += zero ? 0.5 * (double)w : (double)w;
-            A[x * n + y] = zero ? 0.5 * (double)w : 0.0;
+            A[x * n + y] = zero ? to_fixed(0.5 * (double)w, scale) : 0ull;
         }
         red[threadIdx.x] = diag;
         __syncthreads();
@@ -94,7 +110,7 @@ __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, in
             if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) A[x * n + x] = red[0];
+        if (threadIdx.x == 0) A[x * n + x] = to_fixed(red[0], scale);
         __syncthreads();
     }
 }
@@ -131,12 +147,25 @@ __global__ __launch_bounds__(256) void triplet_mirror_u_kernel(int32_t *__restri
     }
 }
 
-// C = fl32(A / (n - 1)).
-__global__ void triplet_finalize_kernel(const double *__restrict__ A, int64_t n, float *__restrict__ C, int64_t ldc) {
+// C = fl32(A 2^-F / (n - 1)).
+__global__ void triplet_finalize_kernel(const unsigned long long *__restrict__ A, int64_t n, float *__restrict__ C,
+                                        int64_t ldc, double inv_scale) {
     const double nm1 = (double)(n - 1);
     for (int64_t x = blockIdx.y; x < n; x += gridDim.y)
         for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < n; z += (int64_t)gridDim.x * blockDim.x)
-            C[x * ldc + z] = (float)(A[x * n + z] / nm1);
+            C[x * ldc + z] = (float)((double)(long long)A[x * n + z] * inv_scale / nm1);
+}
+
+// k -> (bx, bz), bx <= bz < nb, with the owner tiles listed by decreasing
+// bz - bx: an owner streams bz - bx + 1 blocks of middle indices, so the
+// longest tiles start first and the short diagonal ones fill in at the end
+// (longest processing time first).  Diagonal bz - bx = nb - m holds m tiles.
+__device__ __forceinline__ void tri_tile_heavy_first(int32_t k, int32_t nb, int32_t &bx, int32_t &bz) {
+    int64_t m = (int64_t)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+    while (m * (m - 1) / 2 > k) --m;
+    while ((m + 1) * m / 2 <= k) ++m;
+    bx = (int32_t)(k - m * (m - 1) / 2);
+    bz = bx + (nb - (int32_t)m);
 }
 
 // Sum of v over the 16 lanes of a row (lane bits 0-3).
@@ -157,13 +186,14 @@ __device__ __forceinline__ V wave_rows_sum(V v) {
 }
 
 // One owner tile of either pass.  PASS2 = false: focus sizes into U (int32,
-// atomics); PASS2 = true: cohesion sums into A (float64, atomics).
+// atomics); PASS2 = true: cohesion sums into A (64-bit fixed point with scale
+// 2^F, atomics).
 template <bool PASS2>
 __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__restrict__ D, int64_t n, int64_t ldd,
                                                               const float *__restrict__ W, int64_t ldw,
                                                               int32_t *__restrict__ U, int64_t ldu,
-                                                              double *__restrict__ A, int32_t vec_d, int32_t vec_w,
-                                                              int32_t tile0) {
+                                                              unsigned long long *__restrict__ A, int32_t vec_d,
+                                                              int32_t vec_w, int32_t tile0, double scale) {
     constexpr int T = TRI_T, R = TRI_R, KQ = TRI_KQ, NT = TRI_THREADS;
     constexpr int ROW = PASS2 ? 4 * T : 2 * T;     // loaded per q: a | (W_qp) | c | (W_qr)
     constexpr int LDS_ROW = PASS2 ? 6 * T : 2 * T; // staged: ... | W_qp/2 | W_qr/2
@@ -175,7 +205,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
     __shared__ Part qbuf[4][KQ][T][PASS2 ? 2 : 1];  // per-wave (q, r) partials of one stage
 
     int32_t bx, bz;
-    tri_tile(tile0 + (int32_t)blockIdx.x, bx, bz);
+    tri_tile_heavy_first(tile0 + (int32_t)blockIdx.x, (int32_t)((n + T - 1) / T), bx, bz);
     const int64_t X0 = (int64_t)bx * T, Z0 = (int64_t)bz * T;
     const int tid = threadIdx.x;
     const int tx = tid / 16, tz = tid % 16, wave = tid / 64, row = (tid % 64) / 16;
@@ -348,7 +378,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
                     const int64_t pi = p(tz);
                     if (pi < n && v != (Part)0) {
                         if (PASS2) {
-                            unsafeAtomicAdd(&A[pi * n + q], (double)v);
+                            atomicAdd(&A[pi * n + q], to_fixed((double)v, scale));
                         } else {
                             atomicAdd(&U[pi * ldu + q], (int32_t)v);  // p < q: upper triangle only
                         }
@@ -359,7 +389,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
                     for (int i = 1; i < R; ++i)
                         if (tz - R == i) v = tqp[i];
                     const int64_t pi = p(tz - R);
-                    if (pi < n && v != (Part)0) unsafeAtomicAdd(&A[q * n + pi], (double)v);
+                    if (pi < n && v != (Part)0) atomicAdd(&A[q * n + pi], to_fixed((double)v, scale));
                 }
             }
             // (q, r) and (r, q): sum over the wave's p, then stage per wave in LDS
@@ -388,7 +418,7 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
             const Part v = qbuf[0][qq][rl][d] + qbuf[1][qq][rl][d] + qbuf[2][qq][rl][d] + qbuf[3][qq][rl][d];
             if (v == (Part)0) continue;
             if (PASS2) {
-                unsafeAtomicAdd(d == 0 ? &A[q * n + rr] : &A[rr * n + q], (double)v);
+                atomicAdd(d == 0 ? &A[q * n + rr] : &A[rr * n + q], to_fixed((double)v, scale));
             } else {
                 atomicAdd(&U[q * ldu + rr], (int32_t)v);  // q < r: upper triangle only
             }
@@ -405,8 +435,8 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
             if (PASS2) {
                 const double f = (double)spr[i][j] + (double)rpr[i][j];
                 const double g = (double)srp[i][j] + (double)rrp[i][j];
-                if (f != 0.0) unsafeAtomicAdd(&A[p(i) * n + r(j)], f);
-                if (g != 0.0) unsafeAtomicAdd(&A[r(j) * n + p(i)], g);
+                if (f != 0.0) atomicAdd(&A[p(i) * n + r(j)], to_fixed(f, scale));
+                if (g != 0.0) atomicAdd(&A[r(j) * n + p(i)], to_fixed(g, scale));
             } else if (upr[i][j] != 0) {
                 atomicAdd(&U[p(i) * ldu + r(j)], upr[i][j]);  // p < r: upper triangle only
             }

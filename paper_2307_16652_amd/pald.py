@@ -23,7 +23,8 @@ ACCUMS = {"compensated": 0, "f64": 1}
 FLAG_TIMING = 1
 TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
                 "triplet_pass1", "triplet_pass2", "triplet_finalize", "distances", "local_depths",
-                "strong_ties_count", "strong_ties_fill", "graph_distances")
+                "strong_ties_count", "strong_ties_fill", "graph_distances", "rows_pass1", "rows_pass2",
+                "ooc_copies")
 DTYPES = {"float32": 0, "float64": 1}
 METRICS = {"euclidean": 0, "sqeuclidean": 1}
 INPUT_FLAGS = {1: "nan", 2: "inf", 4: "negative", 8: "asymmetric", 16: "nonzero_diagonal"}
@@ -37,6 +38,7 @@ EXPORTED = (
     "pald_batch_graph_create", "pald_batch_graph_launch", "pald_batch_graph_destroy",
     "pald_timings_collect", "pald_distances", "pald_local_depths", "pald_strong_ties",
     "pald_graph_distances_workspace_bytes", "pald_graph_distances", "pald_cohesion_noalloc",
+    "pald_rows_workspace_bytes", "pald_cohesion_rows", "pald_ooc_workspace_bytes", "pald_cohesion_ooc",
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
@@ -148,6 +150,14 @@ def load_library(path: str | None = None):
     lib.pald_cohesion.restype = i32
     lib.pald_cohesion_noalloc.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, opt]
     lib.pald_cohesion_noalloc.restype = i32
+    lib.pald_rows_workspace_bytes.argtypes = [i64, i64, opt]
+    lib.pald_rows_workspace_bytes.restype = sz
+    lib.pald_cohesion_rows.argtypes = [vp, i64, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp, opt]
+    lib.pald_cohesion_rows.restype = i32
+    lib.pald_ooc_workspace_bytes.argtypes = [i64, i64]
+    lib.pald_ooc_workspace_bytes.restype = sz
+    lib.pald_cohesion_ooc.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, sz, vp, opt]
+    lib.pald_cohesion_ooc.restype = i32
     lib.pald_check_input.argtypes = [vp, i64, i64, vp, sz, vp, ctypes.POINTER(ctypes.c_uint32)]
     lib.pald_check_input.restype = i32
     cfgp = ctypes.POINTER(BatchConfig)
@@ -312,6 +322,65 @@ def cohesion_noalloc(D, *, accum: str = "compensated", y_chunks: int = 0, z_chun
         U.data_ptr() if U is not None else None, U.stride(0) if U is not None else 0,
         C.data_ptr(), C.stride(0), _stream_ptr(D.device), ctypes.byref(o))
     _check(st, "pald_cohesion_noalloc")
+    return U, C
+
+
+def rows_workspace_bytes(n: int, rows: int) -> int:
+    return int(load_library().pald_rows_workspace_bytes(int(n), int(rows), None))
+
+
+def cohesion_rows(D, x0: int, x1: int, *, want_u: bool = True, timing: bool = False, ws=None,
+                  out_u=None, out_c=None):
+    """(U rows, C rows) for rows x0 <= x < x1 of D's focus sizes and cohesion: int32 and
+    float32 (x1 - x0) x n tensors (U None if want_u is False)."""
+    torch = _torch()
+    n, ldd = _check_matrix(D)
+    rows = int(x1) - int(x0)
+    if ws is None:
+        nbytes = rows_workspace_bytes(n, rows)
+        if nbytes == 0:
+            raise PaldError(ERR_ARG, "pald_rows_workspace_bytes")
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=D.device)
+    U = None
+    if want_u:
+        U = out_u if out_u is not None else torch.empty((rows, n), dtype=torch.int32, device=D.device)
+    C = out_c if out_c is not None else torch.empty((rows, n), dtype=torch.float32, device=D.device)
+    o = make_options(timing=timing)
+    st = load_library().pald_cohesion_rows(
+        D.data_ptr(), n, ldd, int(x0), int(x1),
+        U.data_ptr() if U is not None else None, U.stride(0) if U is not None else 0,
+        C.data_ptr(), C.stride(0), ws.data_ptr(), ws.numel(), _stream_ptr(D.device), ctypes.byref(o))
+    _check(st, "pald_cohesion_rows")
+    return U, C
+
+
+def ooc_workspace_bytes(n: int, panel_rows: int) -> int:
+    return int(load_library().pald_ooc_workspace_bytes(int(n), int(panel_rows)))
+
+
+def cohesion_ooc(D_host, ws_bytes: int, *, device="cuda:0", want_u: bool = True, timing: bool = False):
+    """(U, C) as host numpy arrays for a float32 distance matrix held in host memory
+    (numpy array or CPU torch tensor, C-contiguous), computed out of core in panels of
+    rows sized to a device workspace of ws_bytes (which this call allocates)."""
+    import numpy as np
+
+    torch = _torch()
+    if isinstance(D_host, torch.Tensor):
+        if D_host.is_cuda:
+            raise TypeError("D_host must be in host memory")
+        D_host = D_host.numpy()
+    D_host = np.ascontiguousarray(D_host, dtype=np.float32)
+    n = D_host.shape[0]
+    if D_host.shape != (n, n):
+        raise ValueError("D_host must be square")
+    U = np.empty((n, n), dtype=np.int32) if want_u else None
+    C = np.empty((n, n), dtype=np.float32)
+    ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=device)
+    o = make_options(timing=timing)
+    st = load_library().pald_cohesion_ooc(
+        D_host.ctypes.data, n, n, U.ctypes.data if U is not None else None, n, C.ctypes.data, n,
+        ws.data_ptr(), ws.numel(), _stream_ptr(ws.device), ctypes.byref(o))
+    _check(st, "pald_cohesion_ooc")
     return U, C
 
 

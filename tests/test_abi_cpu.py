@@ -118,12 +118,49 @@ def test_focus_sizes_and_check_input_bad_args():
     assert lib.pald_check_input(fake, 1, 1, fake, 256, None, None) == pald.ERR_ARG
 
 
+def test_rows_and_ooc_argument_errors():
+    lib = pald.load_library()
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.pald_rows_workspace_bytes(100, 0, None) == 0
+    assert lib.pald_rows_workspace_bytes(100, 101, None) == 0
+    assert lib.pald_rows_workspace_bytes(100, 10, None) >= 100 * 64 * 4
+    assert lib.pald_rows_workspace_bytes(100, 10, _opts(accum="f64")) == 0
+    ws = lib.pald_rows_workspace_bytes(100, 10, None)
+    ok = dict(D=fake, n=100, ldd=100, x0=0, x1=10, U=None, ldu=0, C=fake, ldc=100, ws=fake, ws_bytes=ws)
+
+    def call(opt=None, **kw):
+        a = dict(ok, **kw)
+        return lib.pald_cohesion_rows(a["D"], a["n"], a["ldd"], a["x0"], a["x1"], a["U"], a["ldu"], a["C"],
+                                      a["ldc"], a["ws"], a["ws_bytes"], None, opt)
+
+    assert call(D=None) == pald.ERR_ARG
+    assert call(C=None) == pald.ERR_ARG
+    assert call(x0=-1) == pald.ERR_ARG
+    assert call(x0=10, x1=10) == pald.ERR_ARG
+    assert call(x1=101) == pald.ERR_ARG
+    assert call(ldd=99) == pald.ERR_ARG
+    assert call(U=fake, ldu=99) == pald.ERR_ARG
+    assert call(ws_bytes=ws - 1) == pald.ERR_ARG
+    assert call(ws=ctypes.c_void_p(0x10004)) == pald.ERR_ARG
+    assert call(opt=_opts(variant="triplet")) == pald.ERR_UNSUPPORTED
+    assert call(opt=_opts(y_chunks=2)) == pald.ERR_UNSUPPORTED
+    # out of core: the panel must fit the workspace
+    small = lib.pald_ooc_workspace_bytes(100, 16)
+    assert small > 0 and lib.pald_ooc_workspace_bytes(100, 32) > small
+    assert lib.pald_ooc_workspace_bytes(100, 1000) == lib.pald_ooc_workspace_bytes(100, 100)
+    assert lib.pald_cohesion_ooc(fake, 100, 100, None, 0, fake, 100, fake, small - 1, None, None) == pald.ERR_ARG
+    assert lib.pald_cohesion_ooc(None, 100, 100, None, 0, fake, 100, fake, small, None, None) == pald.ERR_ARG
+    assert lib.pald_cohesion_ooc(fake, 100, 99, None, 0, fake, 100, fake, small, None, None) == pald.ERR_ARG
+    assert lib.pald_cohesion_ooc(fake, 100, 100, None, 0, fake, 100, fake, small, None,
+                                 _opts(accum="f64")) == pald.ERR_UNSUPPORTED
+
+
 def test_timings_collect_without_records():
     lib = pald.load_library()
     k = len(pald.TIMING_KINDS)
     tot = (ctypes.c_double * k)()
     cnt = (ctypes.c_int64 * k)()
-    assert lib.pald_timings_collect(tot, cnt, k) == k == 13
+    assert lib.pald_timings_collect(tot, cnt, k) == k == 16
     assert list(cnt) == [0] * k
 
 

@@ -125,3 +125,24 @@ def test_config_mixture8d_n4096_full():
     err = assert_c_close(C, Co, what="triplet mixture8d n=4096")
     check_invariants(U, C, "triplet mixture8d")
     log(f"  max rel err {err:.3e}")
+
+
+@pytest.mark.parametrize("variant", ["triplet", "hybrid"])
+def test_bitwise_reproducible(variant):
+    """U and C of the triplet and hybrid variants are the same bits on every run:
+    their owners' partial sums are combined with integer (fixed-point) atomics,
+    which commute, so the arrival order of the atomics does not matter."""
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    D = to_gpu(synth.mixture8d(n=1500, seed=81))
+    ws = pald.workspace(1500, D.device, variant=variant)
+    U0, C0 = pald.cohesion(D, variant=variant, ws=ws)
+    U0, C0 = U0.clone(), C0.clone()
+    for rep in range(4):
+        _ = (D * 3.0).sum()  # unrelated work between the runs
+        U, C = pald.cohesion(D, variant=variant, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(U, U0), f"{variant} run {rep}: U differs"
+        assert torch.equal(C.view(torch.int32), C0.view(torch.int32)), f"{variant} run {rep}: C bits differ"

@@ -32,15 +32,17 @@
  *   PALD_ERR_ARG / PALD_ERR_UNSUPPORTED and nothing is enqueued.  A failed
  *   launch reports PALD_ERR_DEVICE.
  * - The hot calls allocate no device memory.  Batch plans own a small device
- *   descriptor allocated at plan creation.
+ *   descriptor allocated at plan creation.  Workspace arguments are device
+ *   memory (hipMalloc or a caller's pool); host or fine-grained memory is not
+ *   supported there.
  * - Comparisons are made on the float32 input values exactly as given, so U
- *   is exact.  C accumulates float32 weights 1/U in float32 runs of 12 terms
+ *   is exact.  C accumulates float32 half weights 1/(2U) in float32 runs
  *   folded into per-tile Kahan-compensated partials; float64 is used only for
  *   the final cross-tile reduction and the 1/(n-1) scaling.  Relative error
- *   of every C entry <= 15 * 2^-24 (8.9e-7); entries whose exact value is 0
- *   are exactly 0.  Results of the pairwise and batched paths are
- *   deterministic for a fixed configuration (the triplet variant's float64
- *   atomics make its last bits order-dependent).
+ *   of every C entry <= 16 * 2^-24 (9.5e-7); entries whose exact value is 0
+ *   are exactly 0.  Results are deterministic for a fixed configuration,
+ *   the triplet variant included (its cross-workgroup sums are exact
+ *   64-bit fixed-point integer additions).
  */
 #ifndef PALD_H
 #define PALD_H

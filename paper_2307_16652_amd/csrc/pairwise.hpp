@@ -19,14 +19,13 @@
 //  * comparisons are made on "keys": the float bits with the sign bit
 //    cleared, which order non-negative floats exactly like the floats
 //    themselves (denormals included, -0 mapped to +0), so min/compare are
-//    single full-rate integer instructions and no select on NaN handling is
-//    needed;
+//    single integer instructions and no select on NaN handling is needed;
 //  * pass 1 uses the symmetry of U: only tiles with bx <= by run and they
 //    write their transpose too;
-//  * pass 2 accumulates float32 runs of 12 terms, folds each run into a Kahan
-//    (sum, compensation) pair, and reduces the pair in float64 at the end;
-//    the worst-case relative error is (12 + 3) * 2^-24 < 1e-6 (rounding of
-//    W, the run, the fold and the final store).
+//  * pass 2 accumulates exact half weights in float32 runs, folds each run
+//    into a Kahan (sum, compensation) pair, and reduces the pair in float64
+//    at the end; the worst-case relative error is below 16 * 2^-24 < 1e-6
+//    (rounding of W, the run, the fold and the final store; see P2_RUN).
 #pragma once
 
 #include <hip/hip_runtime.h>

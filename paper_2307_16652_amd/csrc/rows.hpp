@@ -80,7 +80,7 @@ __device__ __forceinline__ void cohesion_fwd4(float (&rf)[4], const uint32_t (&t
 // float64 accumulator acc[(x - xlo) ldacc + z] (blocks of y streamed one after
 // another).  Grid: blockIdx.x = z tile, blockIdx.y = x tile.
 #ifndef PALD_P2R_RX
-#define PALD_P2R_RX 4
+#define PALD_P2R_RX 2
 #endif
 constexpr int P2R_T = 64, P2R_RX = PALD_P2R_RX, P2R_RZ = 4, P2R_KY = 12, P2R_RUN = 6;
 constexpr int P2R_TX = P2R_T / P2R_RX, P2R_TZ = P2R_T / P2R_RZ, P2R_NT = P2R_TX * P2R_TZ;

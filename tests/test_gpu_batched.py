@@ -220,8 +220,11 @@ def test_unaligned_base_pointer():
 @pytest.mark.parametrize("tile,chunks", [(64, 1), (32, 1), (64, 3)])
 def test_split_pass1(tile, chunks):
     """Pass 1 as its own launch of 16 x 16 lanes-over-z tiles: oracle parity on
-    ragged and tie-heavy sizes, and U and C bit-identical to the one-launch mode
-    (the weights are the same fl32(1/U) and pass 2 is the same code)."""
+    ragged and tie-heavy sizes, U bit-identical to the one-launch mode, and C
+    bit-identical too where both run the general persistent pass-2 kernel (the
+    weights are the same fl32(1/U)); with 64-wide tiles and no y split the split
+    form runs the lean kernel, whose float32 runs are longer (split runs of 12 y,
+    24 y per stage), so C then agrees to the error bound instead."""
     from paper_2307_16652_amd import pald
 
     mats = make_batch(RAGGED, seed=13) + make_batch([4, 40, 96, 161], seed=14, kind="grid")
@@ -232,7 +235,10 @@ def test_split_pass1(tile, chunks):
     _, _, Uf, Cf = run_batch(mats, config=pald.make_batch_config(buckets))
     for i in range(len(mats)):
         assert np.array_equal(Us[i], Uf[i]), f"matrix {i}: U differs between the modes"
-        assert np.array_equal(Cs[i].view(np.int32), Cf[i].view(np.int32)), f"matrix {i}: C differs"
+        if tile == 64 and chunks == 1:
+            assert_c_close(Cs[i], Cf[i], rtol=2e-6, what=f"matrix {i}: lean split vs one-launch C")
+        else:
+            assert np.array_equal(Cs[i].view(np.int32), Cf[i].view(np.int32)), f"matrix {i}: C differs"
 
 
 @pytest.mark.parametrize("buckets", [[(100, 1), (1 << 30, 2)], [(1 << 30, 1, 64)]], ids=["general", "lean"])

@@ -249,7 +249,7 @@ pald_status run_pass2(const float *D, int64_t n, int64_t ldd, const float *W, in
 // ---- triplet variant ---------------------------------------------------------
 struct TripletPlan {
     int64_t tiles = 0, ldw = 0;
-    size_t off_w = 0, off_a = 0, off_u = 0, bytes = 0;
+    size_t off_w = 0, off_a = 0, off_b = 0, off_u = 0, bytes = 0;
 };
 
 TripletPlan triplet_plan(int64_t n) {
@@ -261,6 +261,8 @@ TripletPlan triplet_plan(int64_t n) {
     t.off_w = off;
     off = align_up(off + (size_t)n * (size_t)t.ldw * sizeof(float), ALIGN);
     t.off_a = off;
+    off = align_up(off + (size_t)n * (size_t)n * sizeof(double), ALIGN);
+    t.off_b = off;  // the transposed accumulator B
     off = align_up(off + (size_t)n * (size_t)n * sizeof(double), ALIGN);
     t.off_u = off;
     off = align_up(off + (size_t)n * (size_t)n * sizeof(int32_t), ALIGN);
@@ -281,7 +283,8 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 5, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, vec, 0, (int32_t)t0, 1.0);
+        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, nullptr, vec, 0,
+                                                         (int32_t)t0, 0, 1.0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     // the upper triangle holds U; mirror it
@@ -296,9 +299,11 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
                              void *ws, size_t ws_bytes, hipStream_t s, bool timing) {
     const TripletPlan t = triplet_plan(n);
     if (ws_bytes < t.bytes) return PALD_ERR_ARG;
+    if (n > ((int64_t)1 << 18)) return PALD_ERR_UNSUPPORTED;  // the fixed-point sums are exact up to 2^18 points
     char *base = static_cast<char *>(ws);
     float *W = reinterpret_cast<float *>(base + t.off_w);
     unsigned long long *A = reinterpret_cast<unsigned long long *>(base + t.off_a);
+    unsigned long long *B = reinterpret_cast<unsigned long long *>(base + t.off_b);
     const double scale = std::ldexp(1.0, triplet_fixed_bits(n));
     int32_t *Ub = U;
     int64_t ldub = ldu;
@@ -310,17 +315,20 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
     weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, t.ldw, n);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
-    triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A, scale);
+    triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A, B, scale);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 6, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, vecd, 1, (int32_t)t0, scale);
+        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, B, vecd, 1, (int32_t)t0,
+                                                        triplet_fixed_bits(n), scale);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
     ScopedTiming tm(timing, 7, s);
-    triplet_finalize_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(A, n, C, ldc, 1.0 / scale);
+    const int64_t ftiles = ceil_div(n, 32) * ceil_div(n, 32);
+    triplet_finalize_kernel<<<(unsigned)std::min<int64_t>(ftiles, 65536), 256, 0, s>>>(A, B, n, C, ldc, 1.0 / scale,
+                                                                                      ftiles);
     return launch_status();
 }
 

@@ -19,22 +19,28 @@
 //
 // GPU mapping.  An owner workgroup takes a 64 x 64 block pair (X, Z), X <= Z,
 // and every triple whose smallest index is in X and largest in Z; the middle
-// index q streams through LDS in stages of 16 rows.  Each thread owns 4 x 4
-// pairs (p, r): the (p, r) terms accumulate in registers; the (p, q) terms of a
-// q are summed over the thread's r, then over the 16 lanes that share p (lane
-// shuffles), and added to the float64 accumulator with one atomic per value;
-// the (q, r) terms are summed over the wave's p with shuffles, then over the
-// four waves through LDS.  Every pair's terms come from several owners, so the
-// global sums use integer atomics, which commute: int32 on the upper triangle
-// of U (mirrored to the lower one after the pass) and, for C, 64-bit
-// fixed-point accumulators A with F = 61 - ceil(log2 n) fraction bits.  Each
-// owner's float32 partial sum is a multiple of its last mantissa bit, at
-// least 2^-(ceil(log2 n) + 24) (every term is W_xy or W_xy / 2 with
-// W_xy >= 1/n), so for n <= 2^18 it converts to fixed point exactly, and
-// every sum stays below n/2, so below 2^60 in fixed point.  The result is
-// the exact sum of the owners' partials whatever order the atomics land in:
-// C is bitwise reproducible, and accurate to the same bound as the pairwise
-// path.
+// index q streams through LDS in stages of 8 rows.  Each thread owns 4 x 4
+// pairs (p, r) and runs, per q, a branch-free block per triple: one min and
+// three compares, then float32 adds of half weights under EXEC masks
+// (triplet_cohesion4, triplet_count4).  The (p, r) terms accumulate in
+// registers; the (p, q) terms of a q are summed over the 16 lanes that share
+// p (DPP), the (q, r) terms over the wave's rows (lane swaps), both into LDS,
+// and once per stage the workgroup adds them to the global sums with integer
+// atomics, which commute: int32 for U and, for C, 64-bit fixed-point
+// accumulators with F = 61 - ceil(log2 n) fraction bits.  Every sum lands in
+// row q of its accumulator: u_pq in the lower triangle of U (u_qr, u_pr in
+// the upper one; a last kernel adds the two triangles), c_qp and c_qr in A,
+// c_pq and c_rq transposed in B (C = A + B^T at the end).  The atomics of a
+// wave then touch one or two rows instead of 64 rows n elements apart, which
+// land on few memory channels: with the sums in A alone both passes took
+// 2-3x longer.  Each owner's float32 partial
+// sum is a multiple of 2^-(ceil(log2 n) + 24) (every term is a half weight
+// W_xy / 2 with W_xy >= 1/n, a float32 of 24 bits, and float32 sums of such
+// multiples stay multiples of it), so for n <= 2^18 it converts to fixed
+// point exactly, and every sum stays below n/2, so below 2^60 in fixed
+// point.  The result is the exact sum of the owners' partials whatever order
+// the atomics land in: C is bitwise reproducible, and accurate to the same
+// bound as the pairwise path.
 //
 // On a GPU this variant does fewer comparisons than the pairwise one but
 // moves O(n^3 / 64) partial sums through atomics, where the pairwise tiles
@@ -52,18 +58,25 @@ namespace pald {
 
 constexpr int TRI_T = 64;         // owner tile side
 constexpr int TRI_R = 4;          // 4 x 4 (p, r) per thread
-constexpr int TRI_KQ = 16;        // q rows per LDS stage
+constexpr int TRI_KQ = 8;         // q rows per LDS stage
 constexpr int TRI_THREADS = 256;  // tid = tx * 16 + tz; p = X0 + 4 tx + i, r = Z0 + 4 tz + j
-constexpr int TRI_RUN = 8;        // float32 run length of the (p, r) sums before a Kahan fold
-
-// U_xy = 2 off the diagonal, U_xx = #{z : d_xz <= 0}.
+constexpr int TRI_RUN = 4;        // q values per float32 run of the (p, r) sums (at most 8 half weights)
+// workgroups per CU each pass is compiled for (its register budget)
+#ifndef PALD_TRI_MIN_BLOCKS1
+#define PALD_TRI_MIN_BLOCKS1 4
+#endif
+#ifndef PALD_TRI_MIN_BLOCKS2
+#define PALD_TRI_MIN_BLOCKS2 3
+#endif
+// U_xy = 2 above the diagonal, 0 below it (pass 1 adds into both triangles
+// and triplet_mirror_u_kernel sums them), U_xx = #{z : d_xz <= 0}.
 __global__ void triplet_init_u_kernel(const float *__restrict__ D, int64_t n, int64_t ldd, int32_t *__restrict__ U,
                                       int64_t ldu) {
     __shared__ int32_t red[256];
     for (int64_t x = blockIdx.x; x < n; x += gridDim.x) {
         int32_t cnt = 0;
         for (int64_t y = threadIdx.x; y < n; y += blockDim.x) {
-            U[x * ldu + y] = 2;
+            U[x * ldu + y] = y < x ? 0 : 2;
             cnt += (key_of(D[x * ldd + y]) == 0u) ? 1 : 0;
         }
         red[threadIdx.x] = cnt;
@@ -93,11 +106,13 @@ __device__ __forceinline__ unsigned long long to_fixed(double v, double scale) {
 // with s(p, q) = [p < q] + 1/2 [p == q]; the diagonal sum runs in float64 in a
 // fixed order (tree over the workgroup) and is converted once.
 __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W,
-                                      int64_t ldw, unsigned long long *__restrict__ A, double scale) {
+                                      int64_t ldw, unsigned long long *__restrict__ A,
+                                      unsigned long long *__restrict__ B, double scale) {
     __shared__ double red[256];
     for (int64_t x = blockIdx.x; x < n; x += gridDim.x) {
         double diag = 0.0;
         for (int64_t y = threadIdx.x; y < n; y += blockDim.x) {
+            B[x * n + y] = 0ull;
             if (y == x) continue;
             const bool zero = key_of(D[x * ldd + y]) == 0u;
             const float w = W[x * ldw + y];
@@ -115,10 +130,10 @@ __global__ void triplet_init_c_kernel(const float *__restrict__ D, int64_t n, in
     }
 }
 
-// Pass 1 accumulates only the upper triangle of U (every triple adds to
-// U[lo][hi], lo < hi); this copies it to the lower triangle: U[y][x] = U[x][y]
-// for x < y.  32 x 32 tiles transposed through LDS; tile (ty, tx) with ty > tx
-// reads tile (tx, ty), diagonal tiles mirror within themselves.
+// Pass 1 accumulates into both triangles of U; this makes U symmetric:
+// U[x][y] = U[y][x] = U[x][y] + U[y][x] for x < y.  32 x 32 tiles through
+// LDS; the lower-triangle tile (ty, tx), ty >= tx, pairs with the upper tile
+// (tx, ty), and diagonal tiles pair with themselves.
 __global__ __launch_bounds__(256) void triplet_mirror_u_kernel(int32_t *__restrict__ U, int64_t ldu, int64_t n,
                                                                int32_t tiles) {
     __shared__ int32_t t[32][33];
@@ -130,30 +145,56 @@ __global__ __launch_bounds__(256) void triplet_mirror_u_kernel(int32_t *__restri
         if ((ty + 1) * (ty + 2) / 2 <= k) ++ty;
         const int64_t tx = k - ty * (ty + 1) / 2;
         if (ty >= nb) break;
-        // load source tile (tx, ty): rows tx*32.., columns ty*32..
+        // the upper tile (tx, ty): rows tx*32.., columns ty*32..
         for (int e = threadIdx.x; e < 32 * 32; e += 256) {
             const int i = e / 32, j = e % 32;
             const int64_t row = tx * 32 + i, col = ty * 32 + j;
             t[i][j] = (row < n && col < n) ? U[row * ldu + col] : 0;
         }
         __syncthreads();
-        // write destination tile (ty, tx): U[ty*32 + j][tx*32 + i] = t[i][j] where row < col in the source
+        // the lower tile (ty, tx): U[ty*32 + j][tx*32 + i] pairs with t[i][j] where row < col
         for (int e = threadIdx.x; e < 32 * 32; e += 256) {
             const int j = e / 32, i = e % 32;
             const int64_t srow = tx * 32 + i, scol = ty * 32 + j;
-            if (srow < n && scol < n && srow < scol) U[scol * ldu + srow] = t[i][j];
+            if (srow < n && scol < n && srow < scol) {
+                const int32_t v = t[i][j] + U[scol * ldu + srow];
+                t[i][j] = v;
+                U[scol * ldu + srow] = v;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int i = e / 32, j = e % 32;
+            const int64_t row = tx * 32 + i, col = ty * 32 + j;
+            if (row < n && col < n && row < col) U[row * ldu + col] = t[i][j];
         }
         __syncthreads();
     }
 }
 
-// C = fl32(A 2^-F / (n - 1)).
-__global__ void triplet_finalize_kernel(const unsigned long long *__restrict__ A, int64_t n, float *__restrict__ C,
-                                        int64_t ldc, double inv_scale) {
+// C = fl32((A + B^T) 2^-F / (n - 1)), B read transposed through LDS in
+// 32 x 32 tiles; tile k covers rows 32 (k / nb).. and columns 32 (k % nb).. of C.
+__global__ __launch_bounds__(256) void triplet_finalize_kernel(const unsigned long long *__restrict__ A,
+                                                               const unsigned long long *__restrict__ B, int64_t n,
+                                                               float *__restrict__ C, int64_t ldc, double inv_scale,
+                                                               int64_t tiles) {
+    __shared__ unsigned long long t[32][33];
     const double nm1 = (double)(n - 1);
-    for (int64_t x = blockIdx.y; x < n; x += gridDim.y)
-        for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < n; z += (int64_t)gridDim.x * blockDim.x)
-            C[x * ldc + z] = (float)((double)(long long)A[x * n + z] * inv_scale / nm1);
+    const int64_t nb = (n + 31) / 32;
+    for (int64_t k = blockIdx.x; k < tiles; k += gridDim.x) {
+        const int64_t x0 = (k / nb) * 32, z0 = (k % nb) * 32;
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {  // B[z0 + i][x0 + j]
+            const int i = e / 32, j = e % 32;
+            t[i][j] = (z0 + i < n && x0 + j < n) ? B[(z0 + i) * n + x0 + j] : 0ull;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+            const int i = e / 32, j = e % 32;
+            const int64_t x = x0 + i, z = z0 + j;
+            if (x < n && z < n) C[x * ldc + z] = (float)((double)(long long)(A[x * n + z] + t[j][i]) * inv_scale / nm1);
+        }
+        __syncthreads();
+    }
 }
 
 // k -> (bx, bz), bx <= bz < nb, with the owner tiles listed by decreasing
@@ -168,41 +209,162 @@ __device__ __forceinline__ void tri_tile_heavy_first(int32_t k, int32_t nb, int3
     bz = bx + (nb - (int32_t)m);
 }
 
-// Sum of v over the 16 lanes of a row (lane bits 0-3).
-template <typename V>
-__device__ __forceinline__ V row_sum16(V v) {
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
+// Sum of v over the 16 lanes of a row (lane bits 0-3), by DPP butterflies:
+// quad_perm [1,0,3,2] and [2,3,0,1], then the half-row and row mirrors.
+__device__ __forceinline__ float row_sum16(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
     return v;
 }
-// Sum of v over the 4 rows of a wave (lane bits 4-5).
-template <typename V>
-__device__ __forceinline__ V wave_rows_sum(V v) {
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+// x over lane halves in lanes 0-31, y over lane halves in lanes 32-63:
+// v_permlane32_swap exchanges the upper half of x with the lower half of y.
+__device__ __forceinline__ float halves_sum(float x, float y) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+// x over row pairs (0, 1) and (2, 3) in rows 0 and 2, y in rows 1 and 3:
+// v_permlane16_swap exchanges the odd rows of x with the even rows of y.
+__device__ __forceinline__ float row_pairs_sum(float x, float y) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
 }
 
+// v * 2^fbits as an integer, for v > 0 normal and a multiple of 2^-fbits
+// (exact): v = m 2^(e - 150) with the 24-bit significand m.
+__device__ __forceinline__ unsigned long long fixed_of(float v, int32_t fbits) {
+    const uint32_t bits = __float_as_uint(v);
+    const unsigned long long m = (unsigned long long)((bits & 0x7fffffu) | 0x800000u);
+    const int32_t sh = (int32_t)(bits >> 23) - 150 + fbits;
+    return sh >= 0 ? (m << sh) : (m >> -sh);
+}
+
+// The block of one triple (p, q, r) and three more with the same p and q
+// (the thread's r_0..r_3), registers only.  a = key d_pq, b = key d_pr,
+// c = key d_qr; m = min(a, b, c), e_a = [a == m], e_b = [b == m], e_c =
+// [c == m], computed with EXEC = the lanes whose triple is valid, so that the
+// masks are 0 elsewhere.  Then EXEC takes each mask in turn and the terms are
+// added as half weights (once under e, once more under e minus the tie):
+//   pass 1: u_pq += e_b | e_c, u_pr += e_a | e_c, u_qr += e_a | e_b
+//           (counts in float32, exact below 2^24);
+//   pass 2: c_pq += W_pr/2 (e_a, e_a & ~e_c),  c_qp += W_qr/2 (e_a, e_a & ~e_b),
+//           c_pr += W_pq/2 (e_b, e_b & ~e_c),  c_rp += W_qr/2 (e_b, e_b & ~e_a),
+//           c_qr += W_pq/2 (e_c, e_c & ~e_b),  c_rq += W_pr/2 (e_c, e_c & ~e_a).
+// The last instruction restores EXEC to `full`; the s_nop keeps the lane
+// permutations that read the sums clear of the last writes.
+#define PALD_T_CMP(k, e)                                                                                         \
+    "s_and_b64 exec, %[vp], %[vr" #k "]\n\t"                                                                  \
+    "v_min3_u32 %[m], %[a], %[b" #k "], %[c" #k "]\n\t"                                                       \
+    "v_cmp_eq_u32_e64 %[ea" #e "], %[a], %[m]\n\t"                                                            \
+    "v_cmp_eq_u32_e64 %[eb" #e "], %[b" #k "], %[m]\n\t"                                                      \
+    "v_cmp_eq_u32_e64 %[ec" #e "], %[c" #k "], %[m]\n\t"
+#define PALD_T_U(k, e)                                                                                              \
+    "s_or_b64 exec, %[eb" #e "], %[ec" #e "]\n\t"                                                             \
+    "v_add_f32 %[tpq], 1.0, %[tpq]\n\t"                                                                        \
+    "s_or_b64 exec, %[ea" #e "], %[ec" #e "]\n\t"                                                             \
+    "v_add_f32 %[rf" #k "], 1.0, %[rf" #k "]\n\t"                                                             \
+    "s_or_b64 exec, %[ea" #e "], %[eb" #e "]\n\t"                                                             \
+    "v_add_f32 %[tqr" #k "], 1.0, %[tqr" #k "]\n\t"
+#define PALD_T_C(k, e)                                                                                              \
+    "s_mov_b64 exec, %[ea" #e "]\n\t"                                                                         \
+    "v_add_f32 %[tpq], %[tpq], %[hpr" #k "]\n\t"                                                              \
+    "v_add_f32 %[tqp], %[tqp], %[hc" #k "]\n\t"                                                               \
+    "s_andn2_b64 exec, %[ea" #e "], %[ec" #e "]\n\t"                                                          \
+    "v_add_f32 %[tpq], %[tpq], %[hpr" #k "]\n\t"                                                              \
+    "s_andn2_b64 exec, %[ea" #e "], %[eb" #e "]\n\t"                                                          \
+    "v_add_f32 %[tqp], %[tqp], %[hc" #k "]\n\t"                                                               \
+    "s_mov_b64 exec, %[eb" #e "]\n\t"                                                                         \
+    "v_add_f32 %[rf" #k "], %[rf" #k "], %[ha]\n\t"                                                           \
+    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hc" #k "]\n\t"                                                     \
+    "s_andn2_b64 exec, %[eb" #e "], %[ec" #e "]\n\t"                                                          \
+    "v_add_f32 %[rf" #k "], %[rf" #k "], %[ha]\n\t"                                                           \
+    "s_andn2_b64 exec, %[eb" #e "], %[ea" #e "]\n\t"                                                          \
+    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hc" #k "]\n\t"                                                     \
+    "s_mov_b64 exec, %[ec" #e "]\n\t"                                                                         \
+    "v_add_f32 %[tqr" #k "], %[tqr" #k "], %[ha]\n\t"                                                         \
+    "v_add_f32 %[trq" #k "], %[trq" #k "], %[hpr" #k "]\n\t"                                                  \
+    "s_andn2_b64 exec, %[ec" #e "], %[eb" #e "]\n\t"                                                          \
+    "v_add_f32 %[tqr" #k "], %[tqr" #k "], %[ha]\n\t"                                                         \
+    "s_andn2_b64 exec, %[ec" #e "], %[ea" #e "]\n\t"                                                          \
+    "v_add_f32 %[trq" #k "], %[trq" #k "], %[hpr" #k "]\n\t"
+#define PALD_T_MASKS(e) [ea##e] "=&s"(ea[e]), [eb##e] "=&s"(eb[e]), [ec##e] "=&s"(ec[e])
+#define PALD_T_IN(k) [b##k] "v"(b[k]), [c##k] "v"(c[k]), [vr##k] "s"(vr[k])
+#define PALD_T_IN2(k) [hpr##k] "v"(hpr[k]), [hc##k] "v"(hc[k])
+
+__device__ __forceinline__ void triplet_count4(float &tpq, float (&rf)[4], float (&tqr)[4], uint32_t a,
+                                               const uint32_t (&b)[4], const uint32_t (&c)[4], uint64_t vp,
+                                               const uint64_t (&vr)[4], uint64_t full) {
+    uint64_t ea[2], eb[2], ec[2];
+    uint32_t m;
+    asm volatile(PALD_T_CMP(0, 0) PALD_T_CMP(1, 1) PALD_T_U(0, 0) PALD_T_CMP(2, 0) PALD_T_U(1, 1)
+                 PALD_T_CMP(3, 1) PALD_T_U(2, 0) PALD_T_U(3, 1)
+                 "s_mov_b64 exec, %[full]\n\t"
+                 "s_nop 4"
+                 : [tpq] "+v"(tpq), [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]), [rf3] "+v"(rf[3]),
+                   [tqr0] "+v"(tqr[0]), [tqr1] "+v"(tqr[1]), [tqr2] "+v"(tqr[2]), [tqr3] "+v"(tqr[3]),
+                   [m] "=&v"(m), PALD_T_MASKS(0), PALD_T_MASKS(1)
+                 : [a] "v"(a), [vp] "s"(vp), [full] "s"(full), PALD_T_IN(0), PALD_T_IN(1), PALD_T_IN(2),
+                   PALD_T_IN(3)
+                 : "scc");
+}
+
+__device__ __forceinline__ void triplet_cohesion4(float &tpq, float &tqp, float (&rf)[4], float (&rr)[4],
+                                                  float (&tqr)[4], float (&trq)[4], uint32_t a, float ha,
+                                                  const uint32_t (&b)[4], const float (&hpr)[4],
+                                                  const uint32_t (&c)[4], const float (&hc)[4], uint64_t vp,
+                                                  const uint64_t (&vr)[4], uint64_t full) {
+    uint64_t ea[2], eb[2], ec[2];
+    uint32_t m;
+    asm volatile(PALD_T_CMP(0, 0) PALD_T_CMP(1, 1) PALD_T_C(0, 0) PALD_T_CMP(2, 0) PALD_T_C(1, 1)
+                 PALD_T_CMP(3, 1) PALD_T_C(2, 0) PALD_T_C(3, 1)
+                 "s_mov_b64 exec, %[full]\n\t"
+                 "s_nop 4"
+                 : [tpq] "+v"(tpq), [tqp] "+v"(tqp), [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]),
+                   [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]), [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]),
+                   [tqr0] "+v"(tqr[0]), [tqr1] "+v"(tqr[1]), [tqr2] "+v"(tqr[2]), [tqr3] "+v"(tqr[3]),
+                   [trq0] "+v"(trq[0]), [trq1] "+v"(trq[1]), [trq2] "+v"(trq[2]), [trq3] "+v"(trq[3]),
+                   [m] "=&v"(m), PALD_T_MASKS(0), PALD_T_MASKS(1)
+                 : [a] "v"(a), [ha] "v"(ha), [vp] "s"(vp), [full] "s"(full), PALD_T_IN(0), PALD_T_IN(1),
+                   PALD_T_IN(2), PALD_T_IN(3), PALD_T_IN2(0), PALD_T_IN2(1), PALD_T_IN2(2), PALD_T_IN2(3)
+                 : "scc");
+}
+#undef PALD_T_CMP
+#undef PALD_T_U
+#undef PALD_T_C
+#undef PALD_T_MASKS
+#undef PALD_T_IN
+#undef PALD_T_IN2
+
 // One owner tile of either pass.  PASS2 = false: focus sizes into U (int32,
-// atomics); PASS2 = true: cohesion sums into A (64-bit fixed point with scale
-// 2^F, atomics).
+// atomics, upper triangle); PASS2 = true: cohesion sums into A (64-bit fixed
+// point with fbits fraction bits, atomics).
+//
+// Per middle index q a thread runs the blocks of its 4 x 4 triples (p_i, q,
+// r_j); the (p, r) terms stay in its registers, the (p, q) terms are summed
+// over the 16 lanes that share p (DPP) into a per-stage LDS buffer, and the
+// (q, r) terms over the wave's 4 rows (lane swaps; each row ends up with a
+// different pair of sums) into per-wave LDS buffers.  After each stage of KQ
+// rows of q the workgroup adds the stage's (p, q) and (q, r) sums (the four
+// waves' partials in wave order) to the global sums.  Stages whose q lie
+// between the two blocks need no index masks.
 template <bool PASS2>
-__global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__restrict__ D, int64_t n, int64_t ldd,
-                                                              const float *__restrict__ W, int64_t ldw,
-                                                              int32_t *__restrict__ U, int64_t ldu,
-                                                              unsigned long long *__restrict__ A, int32_t vec_d,
-                                                              int32_t vec_w, int32_t tile0, double scale) {
+__global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TRI_MIN_BLOCKS1) void triplet_kernel(
+    const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
+    int32_t *__restrict__ U, int64_t ldu, unsigned long long *__restrict__ A, unsigned long long *__restrict__ B,
+    int32_t vec_d, int32_t vec_w, int32_t tile0, int32_t fbits, double scale) {
     constexpr int T = TRI_T, R = TRI_R, KQ = TRI_KQ, NT = TRI_THREADS;
-    constexpr int ROW = PASS2 ? 4 * T : 2 * T;     // loaded per q: a | (W_qp) | c | (W_qr)
-    constexpr int LDS_ROW = PASS2 ? 6 * T : 2 * T; // staged: ... | W_qp/2 | W_qr/2
-    constexpr int VPC = KQ * ROW / 4;              // uint4 loaded per stage
+    constexpr int LROW = PASS2 ? 4 * T : 2 * T;  // per q: a | W_qp/2 | c | W_qr/2  (pass 1: a | c)
+    constexpr int CSEG = PASS2 ? 2 * T : T;      // offset of c in a row
+    constexpr int ND = PASS2 ? 2 : 1;            // (p, q) and (q, p); (q, r) and (r, q)
+    constexpr int VPC = KQ * LROW / 4;           // uint4 per stage
     constexpr int VPT = VPC / NT;
     static_assert(VPC % NT == 0, "stage must split evenly");
-    using Part = typename std::conditional<PASS2, float, int32_t>::type;
-    __shared__ uint4 sm[2 * KQ * LDS_ROW / 4];
-    __shared__ Part qbuf[4][KQ][T][PASS2 ? 2 : 1];  // per-wave (q, r) partials of one stage
+    static_assert(KQ % TRI_RUN == 0, "stages hold whole runs");
+    static_assert(R == 4 && T == 64 && NT == 256, "the lane reductions assume 4 x 4 per thread, 16 x 16 threads");
+    __shared__ uint4 sm[2 * KQ * LROW / 4];
+    __shared__ float pbuf[KQ][ND][T];     // (p, q) sums of the stage, by p
+    __shared__ float qbuf[4][KQ][ND][T];  // per-wave (q, r) sums of the stage, by r
 
     int32_t bx, bz;
     tri_tile_heavy_first(tile0 + (int32_t)blockIdx.x, (int32_t)((n + T - 1) / T), bx, bz);
@@ -210,38 +372,35 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
     const int tid = threadIdx.x;
     const int tx = tid / 16, tz = tid % 16, wave = tid / 64, row = (tid % 64) / 16;
     const bool diag_owner = bx == bz;
+    const uint64_t full = __builtin_amdgcn_read_exec();
 
-    // p_i = X0 + 4 tx + i, r_j = Z0 + 4 tz + j (recomputed where used: no
-    // registers held for them across the q loop)
     auto p = [&](int i) { return X0 + tx * R + i; };
     auto r = [&](int j) { return Z0 + tz * R + j; };
-    // stationary (p, r) data
+    // stationary (p, r) data: keys and half weights
     uint32_t b[R][R];
-    float wpr[R][R];
+    float hpr[R][R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const bool in = p(i) < n && r(j) < n;
             b[i][j] = in ? key_of(D[p(i) * ldd + r(j)]) : 0u;
-            const float w = (PASS2 && in) ? W[p(i) * ldw + r(j)] : 0.0f;
-            wpr[i][j] = w;
+            hpr[i][j] = (PASS2 && in) ? 0.5f * W[p(i) * ldw + r(j)] : 0.0f;
         }
-    // (p, r) accumulators: float32 runs r and Kahan sums s (a run starts from
-    // the negated compensation of the previous fold, as in the pairwise pass 2)
-    int32_t upr[R][R];
-    float rpr[R][R], rrp[R][R], spr[R][R], srp[R][R];
+    uint64_t rn[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) rn[j] = lane_mask(r(j) < n);
+    // (p, r) accumulators: pass 1 counts in rf; pass 2 float32 runs rf (c_pr)
+    // and rr (c_rp) with Kahan sums sf, sr (a run starts from the negated
+    // compensation of the previous fold)
+    float rf[R][R], rr[R][R], sf[R][R], sr[R][R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            upr[i][j] = 0;
-            rpr[i][j] = rrp[i][j] = 0.0f;
-            spr[i][j] = srp[i][j] = 0.0f;
-        }
+        for (int j = 0; j < R; ++j) rf[i][j] = rr[i][j] = sf[i][j] = sr[i][j] = 0.0f;
 
-    // the middle index runs over [X0, min(n, Z0 + T)); triples outside p < q < r
-    // (or with r >= n) are masked out
+    // the middle index runs over [X0, min(n, Z0 + T)); triples outside
+    // p < q < r < n are masked out
     const int64_t qlo = X0, qhi = min(n, Z0 + T);
     const int64_t nst = (qhi - qlo + KQ - 1) / KQ;
 
@@ -250,37 +409,29 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int v = tid + k * NT;
-            const int rr = v / (ROW / 4), g = v % (ROW / 4);
+            const int rw = v / (LROW / 4), g = v % (LROW / 4);
             const int seg = g / (T / 4);
-            const int64_t q = qc + rr;
-            if (PASS2) {
-                const int64_t col = ((seg < 2) ? X0 : Z0) + 4 * (g % (T / 4));
-                if (seg == 0 || seg == 2)
-                    pre[k] = load_keys4(D, ldd, q, col, qhi, n, vec_d != 0, 0u);
-                else
-                    pre[k] = load_vals4(W, ldw, q, col, qhi, n, vec_w != 0);
-            } else {
-                const int64_t col = ((seg < 1) ? X0 : Z0) + 4 * (g % (T / 4));
+            const int64_t q = qc + rw;
+            const int64_t col = ((seg < ND) ? X0 : Z0) + 4 * (g % (T / 4));
+            if (PASS2 && (seg & 1))
+                pre[k] = load_vals4(W, ldw, q, col, qhi, n, vec_w != 0);
+            else
                 pre[k] = load_keys4(D, ldd, q, col, qhi, n, vec_d != 0, 0u);
-            }
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             const int v = tid + k * NT;
-            const int rr = v / (ROW / 4), g = v % (ROW / 4);
-            uint4 *dst = sm + buf * (KQ * LDS_ROW / 4) + rr * (LDS_ROW / 4);
-            dst[g] = pre[k];
-            if (PASS2) {
-                const int seg = g / (T / 4);
-                if (seg == 1 || seg == 3) {
-                    const uint4 w = pre[k];
-                    dst[T + (seg == 1 ? 0 : T / 4) + g % (T / 4)] = make_uint4(
-                        __float_as_uint(0.5f * __uint_as_float(w.x)), __float_as_uint(0.5f * __uint_as_float(w.y)),
-                        __float_as_uint(0.5f * __uint_as_float(w.z)), __float_as_uint(0.5f * __uint_as_float(w.w)));
-                }
-            }
+            const int rw = v / (LROW / 4), g = v % (LROW / 4);
+            const int seg = g / (T / 4);
+            uint4 w = pre[k];
+            if (PASS2 && (seg & 1))  // weights staged halved (exact)
+                w = make_uint4(__float_as_uint(0.5f * __uint_as_float(w.x)),
+                               __float_as_uint(0.5f * __uint_as_float(w.y)),
+                               __float_as_uint(0.5f * __uint_as_float(w.z)),
+                               __float_as_uint(0.5f * __uint_as_float(w.w)));
+            sm[buf * (KQ * LROW / 4) + rw * (LROW / 4) + g] = w;
         }
     };
 
@@ -294,133 +445,107 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
         const int buf = (int)(st & 1);
         const int64_t qc = qlo + st * KQ;
         if (st + 1 < nst) fetch(qc + KQ);
-        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (KQ * LDS_ROW / 4));
+        const bool interior = qc >= X0 + T && qc + KQ <= Z0;
+        const uint32_t *s = reinterpret_cast<const uint32_t *>(sm + buf * (KQ * LROW / 4));
 #pragma unroll 1
-        for (int qq = 0; qq < KQ; ++qq) {
+        for (int h = 0; h < KQ; h += TRI_RUN) {
+#pragma unroll 1
+        for (int qq = h; qq < h + TRI_RUN; ++qq) {
             const int64_t q = qc + qq;
-            const uint32_t *rowp = s + qq * LDS_ROW;
-            uint32_t av[R], cv[R];
-            float wpq[R], whpq[R], wqr[R], whqr[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                av[i] = rowp[tx * R + i];
-                cv[i] = rowp[(PASS2 ? 2 : 1) * T + tz * R + i];
-                if (PASS2) {
-                    wpq[i] = __uint_as_float(rowp[T + tx * R + i]);
-                    wqr[i] = __uint_as_float(rowp[3 * T + tz * R + i]);
-                    whpq[i] = __uint_as_float(rowp[4 * T + tx * R + i]);
-                    whqr[i] = __uint_as_float(rowp[5 * T + tz * R + i]);
-                }
-            }
+            const uint32_t *rowp = s + qq * LROW;
+            const uint4 a4 = *reinterpret_cast<const uint4 *>(rowp + tx * R);
+            const uint4 c4 = *reinterpret_cast<const uint4 *>(rowp + CSEG + tz * R);
+            const uint32_t av[R] = {a4.x, a4.y, a4.z, a4.w};
+            const uint32_t cv[R] = {c4.x, c4.y, c4.z, c4.w};
             uint64_t vp[R], vr[R];
+            if (interior) {
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-                vp[i] = lane_mask(p(i) < q);
-                vr[i] = lane_mask(q < r(i) && r(i) < n);
-            }
-            Part tpq[R], tqp[R], tqr[R], trq[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) tpq[i] = tqp[i] = tqr[i] = trq[i] = (Part)0;
-#pragma unroll
-            for (int i = 0; i < R; ++i)
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    const uint64_t valid = vp[i] & vr[j];
-                    const uint32_t m = umin(av[i], umin(b[i][j], cv[j]));
-                    const uint64_t ea = lane_mask(av[i] == m) & valid;
-                    const uint64_t eb = lane_mask(b[i][j] == m) & valid;
-                    const uint64_t ec = lane_mask(cv[j] == m) & valid;
-                    if (!PASS2) {
-                        tpq[i] += lane_bit(eb | ec) ? 1 : 0;
-                        upr[i][j] += lane_bit(ea | ec) ? 1 : 0;
-                        tqr[j] += lane_bit(ea | eb) ? 1 : 0;
-                    } else {
-                        const float t1 = lane_bit(eb) ? (lane_bit(ec) ? whpq[i] : wpq[i]) : 0.0f;  // c_pr
-                        const float t2 = lane_bit(ec) ? (lane_bit(eb) ? whpq[i] : wpq[i]) : 0.0f;  // c_qr
-                        const float whpr = 0.5f * wpr[i][j];  // exact; not kept across q
-                        const float t3 = lane_bit(ea) ? (lane_bit(ec) ? whpr : wpr[i][j]) : 0.0f;  // c_pq
-                        const float t4 = lane_bit(ec) ? (lane_bit(ea) ? whpr : wpr[i][j]) : 0.0f;  // c_rq
-                        const float t5 = lane_bit(ea) ? (lane_bit(eb) ? whqr[j] : wqr[j]) : 0.0f;  // c_qp
-                        const float t6 = lane_bit(eb) ? (lane_bit(ea) ? whqr[j] : wqr[j]) : 0.0f;  // c_rp
-                        rpr[i][j] += t1;
-                        rrp[i][j] += t6;
-                        tpq[i] += t3;
-                        tqp[i] += t5;
-                        tqr[j] += t2;
-                        trq[j] += t4;
-                    }
+                for (int i = 0; i < R; ++i) {
+                    vp[i] = full;
+                    vr[i] = rn[i];
                 }
-            if (PASS2 && (qq % TRI_RUN) == TRI_RUN - 1) {
+            } else {
+                const int32_t qx = (int32_t)(q - X0), qz = (int32_t)(q - Z0);
 #pragma unroll
-                for (int i = 0; i < R; ++i)
-#pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        float tk = spr[i][j] + rpr[i][j];
-                        rpr[i][j] = rpr[i][j] - (tk - spr[i][j]);
-                        spr[i][j] = tk;
-                        tk = srp[i][j] + rrp[i][j];
-                        rrp[i][j] = rrp[i][j] - (tk - srp[i][j]);
-                        srp[i][j] = tk;
-                    }
+                for (int i = 0; i < R; ++i) {
+                    vp[i] = lane_mask(tx * R + i < qx);
+                    vr[i] = lane_mask(qz < tz * R + i) & rn[i];
+                }
             }
-            // (p, q) and (q, p): sum over the 16 lanes sharing p; lane tz = k emits value k
+            float tpq[R], tqp[R], tqr[R] = {0.0f, 0.0f, 0.0f, 0.0f}, trq[R] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if constexpr (PASS2) {
+                const float4 ha4 = *reinterpret_cast<const float4 *>(rowp + T + tx * R);
+                const float4 hc4 = *reinterpret_cast<const float4 *>(rowp + 3 * T + tz * R);
+                const float hav[R] = {ha4.x, ha4.y, ha4.z, ha4.w};
+                const float hcv[R] = {hc4.x, hc4.y, hc4.z, hc4.w};
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    tpq[i] = tqp[i] = 0.0f;
+                    triplet_cohesion4(tpq[i], tqp[i], rf[i], rr[i], tqr, trq, av[i], hav[i], b[i], hpr[i], cv, hcv,
+                                      vp[i], vr, full);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    tpq[i] = 0.0f;
+                    triplet_count4(tpq[i], rf[i], tqr, av[i], b[i], cv, vp[i], vr, full);
+                }
+            }
+            // (p, q) [and (q, p)]: sums over the 16 lanes sharing p, stored by lane 0 [and 1] of the row
 #pragma unroll
             for (int i = 0; i < R; ++i) {
                 tpq[i] = row_sum16(tpq[i]);
                 if (PASS2) tqp[i] = row_sum16(tqp[i]);
             }
-            if (q < n) {
-                if (tz < R) {
-                    Part v = tpq[0];
+            if (tz == 0) *reinterpret_cast<float4 *>(&pbuf[qq][0][tx * R]) = make_float4(tpq[0], tpq[1], tpq[2], tpq[3]);
+            if (PASS2 && tz == 1)
+                *reinterpret_cast<float4 *>(&pbuf[qq][ND - 1][tx * R]) = make_float4(tqp[0], tqp[1], tqp[2], tqp[3]);
+            // (q, r) [and (r, q)]: sums over the wave's 4 rows; row k keeps
+            // pass 2: direction k / 2, r_j for j = 2 (k % 2) + {0, 1}; pass 1: r_k
+            if constexpr (PASS2) {
+                float u[R];
 #pragma unroll
-                    for (int i = 1; i < R; ++i)
-                        if (tz == i) v = tpq[i];
-                    const int64_t pi = p(tz);
-                    if (pi < n && v != (Part)0) {
-                        if (PASS2) {
-                            atomicAdd(&A[pi * n + q], to_fixed((double)v, scale));
-                        } else {
-                            atomicAdd(&U[pi * ldu + q], (int32_t)v);  // p < q: upper triangle only
-                        }
-                    }
-                } else if (PASS2 && tz < 2 * R) {
-                    Part v = tqp[0];
-#pragma unroll
-                    for (int i = 1; i < R; ++i)
-                        if (tz - R == i) v = tqp[i];
-                    const int64_t pi = p(tz - R);
-                    if (pi < n && v != (Part)0) atomicAdd(&A[q * n + pi], to_fixed((double)v, scale));
-                }
+                for (int j = 0; j < R; ++j) u[j] = halves_sum(tqr[j], trq[j]);
+                const float v0 = row_pairs_sum(u[0], u[2]), v1 = row_pairs_sum(u[1], u[3]);
+                *reinterpret_cast<float2 *>(&qbuf[wave][qq][row >> 1][tz * R + 2 * (row & 1)]) = make_float2(v0, v1);
+            } else {
+                const float w0 = halves_sum(tqr[0], tqr[2]), w1 = halves_sum(tqr[1], tqr[3]);
+                qbuf[wave][qq][0][tz * R + row] = row_pairs_sum(w0, w1);
             }
-            // (q, r) and (r, q): sum over the wave's p, then stage per wave in LDS
+        }
+        if constexpr (PASS2) {  // end of a run: fold it into the Kahan sums
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                tqr[j] = wave_rows_sum(tqr[j]);
-                if (PASS2) trq[j] = wave_rows_sum(trq[j]);
-            }
-            if (row == 0) {
+            for (int i = 0; i < R; ++i)
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    qbuf[wave][qq][tz * R + j][0] = tqr[j];
-                    if (PASS2) qbuf[wave][qq][tz * R + j][PASS2 ? 1 : 0] = trq[j];
+                    float tk = sf[i][j] + rf[i][j];
+                    rf[i][j] = rf[i][j] - (tk - sf[i][j]);
+                    sf[i][j] = tk;
+                    tk = sr[i][j] + rr[i][j];
+                    rr[i][j] = rr[i][j] - (tk - sr[i][j]);
+                    sr[i][j] = tk;
                 }
-            }
+        }
         }
         if (st + 1 < nst) stash(buf ^ 1);
         __syncthreads();
-        // sum the four waves' (q, r) partials of this stage and add them
-        for (int e = tid; e < KQ * T * (PASS2 ? 2 : 1); e += NT) {
-            const int d = PASS2 ? (e % 2) : 0;
-            const int rl = (PASS2 ? e / 2 : e) % T;
-            const int qq = (PASS2 ? e / 2 : e) / T;
-            const int64_t q = qc + qq, rr = Z0 + rl;
-            if (q >= n || rr >= n) continue;
-            const Part v = qbuf[0][qq][rl][d] + qbuf[1][qq][rl][d] + qbuf[2][qq][rl][d] + qbuf[3][qq][rl][d];
-            if (v == (Part)0) continue;
+        // add the stage's (p, q) and (q, r) sums
+#pragma unroll 1
+        for (int e = tid; e < KQ * ND * T; e += NT) {
+            const int l = e % T, d = (e / T) % ND, qq = e / (ND * T);
+            const int64_t q = qc + qq;
+            if (q >= qhi) continue;
+            const int64_t pp = X0 + l, rz = Z0 + l;
+            const float v = pbuf[qq][d][l];
+            const float w = ((qbuf[0][qq][d][l] + qbuf[1][qq][d][l]) + qbuf[2][qq][d][l]) + qbuf[3][qq][d][l];
             if (PASS2) {
-                atomicAdd(d == 0 ? &A[q * n + rr] : &A[rr * n + q], to_fixed((double)v, scale));
+                // c_pq into B[q][p], c_qp into A[q][p], c_qr into A[q][r], c_rq into B[q][r]
+                if (v != 0.0f) atomicAdd(d == 0 ? &B[q * n + pp] : &A[q * n + pp], fixed_of(v, fbits));
+                if (w != 0.0f) atomicAdd(d == 0 ? &A[q * n + rz] : &B[q * n + rz], fixed_of(w, fbits));
             } else {
-                atomicAdd(&U[q * ldu + rr], (int32_t)v);  // q < r: upper triangle only
+                // u_pq into U[q][p] (lower triangle), u_qr into U[q][r] (upper triangle)
+                if (v != 0.0f) atomicAdd(&U[q * ldu + pp], (int32_t)v);
+                if (w != 0.0f) atomicAdd(&U[q * ldu + rz], (int32_t)w);
             }
         }
         __syncthreads();
@@ -433,12 +558,12 @@ __global__ __launch_bounds__(TRI_THREADS, 2) void triplet_kernel(const float *__
         for (int j = 0; j < R; ++j) {
             if (p(i) >= n || r(j) >= n || (diag_owner && p(i) >= r(j))) continue;
             if (PASS2) {
-                const double f = (double)spr[i][j] + (double)rpr[i][j];
-                const double g = (double)srp[i][j] + (double)rrp[i][j];
+                const double f = (double)sf[i][j] + (double)rf[i][j];
+                const double g = (double)sr[i][j] + (double)rr[i][j];
                 if (f != 0.0) atomicAdd(&A[p(i) * n + r(j)], to_fixed(f, scale));
-                if (g != 0.0) atomicAdd(&A[r(j) * n + p(i)], to_fixed(g, scale));
-            } else if (upr[i][j] != 0) {
-                atomicAdd(&U[p(i) * ldu + r(j)], upr[i][j]);  // p < r: upper triangle only
+                if (g != 0.0) atomicAdd(&B[p(i) * n + r(j)], to_fixed(g, scale));  // c_rp
+            } else if (rf[i][j] != 0.0f) {
+                atomicAdd(&U[p(i) * ldu + r(j)], (int32_t)rf[i][j]);  // p < r: upper triangle
             }
         }
 }

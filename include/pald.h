@@ -129,7 +129,9 @@ pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd,
  *   ws   device workspace of at least pald_workspace_bytes(n, opt) bytes; its
  *        contents on entry are ignored and on exit unspecified
  * Errors: PALD_ERR_ARG for null D/C/ws, n < 2, a leading dimension < n, small
- * ws; PALD_ERR_UNSUPPORTED for an unknown variant/accum or nonzero reserved.
+ * ws; PALD_ERR_UNSUPPORTED for an unknown variant/accum or nonzero reserved,
+ * and for the triplet variant above n = 2^18 (its 64-bit fixed-point sums are
+ * exact up to there).
  */
 pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd,
                           int32_t *U, int64_t ldu,

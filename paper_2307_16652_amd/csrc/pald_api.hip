@@ -297,9 +297,9 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
 
 pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
                              void *ws, size_t ws_bytes, hipStream_t s, bool timing) {
+    if (n > ((int64_t)1 << 18)) return PALD_ERR_UNSUPPORTED;  // the fixed-point sums are exact up to 2^18 points
     const TripletPlan t = triplet_plan(n);
     if (ws_bytes < t.bytes) return PALD_ERR_ARG;
-    if (n > ((int64_t)1 << 18)) return PALD_ERR_UNSUPPORTED;  // the fixed-point sums are exact up to 2^18 points
     char *base = static_cast<char *>(ws);
     float *W = reinterpret_cast<float *>(base + t.off_w);
     unsigned long long *A = reinterpret_cast<unsigned long long *>(base + t.off_a);

@@ -103,6 +103,10 @@ def test_unknown_options_rejected():
     o = pald.make_options()
     o.flags = 0x80
     assert lib.pald_focus_sizes(fake, 8, 8, fake, 8, None, ctypes.byref(o)) == pald.ERR_UNSUPPORTED
+    # the triplet variant's fixed-point sums are exact up to n = 2^18 only
+    big = (1 << 18) + 1
+    assert lib.pald_cohesion(fake, big, big, None, 0, fake, big, fake, 1 << 62, None,
+                             _opts(variant="triplet")) == pald.ERR_UNSUPPORTED
     o = pald.make_options()
     o.y_chunks = -1
     assert lib.pald_workspace_bytes(8, ctypes.byref(o)) == 0

@@ -11,11 +11,15 @@ Prints ONE JSON line on stdout.  `value` is triplet comparisons per second in
 G/s: 2 n^3 comparison terms per evaluation (one per ordered pair and third
 point in each of the two defining sums) divided by the time per step.
 
-`roofline` describes the dominant kernel (pass 2, cohesion), whose launches
-are timed with HIP events on the stream they run on.  Its algorithmic work is
-4 lane-operations per cohesion term (x, y, z), y != x: the three comparisons
+`roofline` describes the dominant kernel (pass 2, cohesion: the pairwise
+kernel, or the triplet one where the library's tuned choice of variant runs
+the pairwise pass 1 with the triplet pass 2), whose launches are timed with
+HIP events on the stream they run on.  Its algorithmic work is 4
+lane-operations per cohesion term (x, y, z), y != x: the three comparisons
 the tie-exact term needs ([t <= a], [t <= b], [t < b] with t = d_xz, a = d_xy,
-b = d_zy) and one accumulate -- 4 n^2 (n-1) per step.  The peak is the vector
+b = d_zy) and one accumulate -- 4 n^2 (n-1) per step, whichever kernel runs
+(the triplet kernel shares one min and three compares among the six terms of
+a triple, so it issues fewer lane-ops per term than that count).  The peak is the vector
 issue capacity of the chip: 256 CUs x 4 SIMDs x 64 lanes x 2 wave64
 instructions per 4 cycles x 2.4 GHz = 78.64 T lane-ops/s (the published
 157.3 TFLOP/s float32 vector rate, an FMA counting 2).  `bench.py
@@ -25,8 +29,8 @@ instruction, compares, min/max and selects at about 4.2 (half rate, 39.32 T
 lane-ops/s), with float32 additions issuing beside them.  `compare_pipe`
 sets the method's comparisons (3 per term) against that half-rate class.
 `traffic`, and the issued vector instructions per term, are from rocprofv3
-(profiles/pass2_cohesion__grid3d_n16384.json), reported only while the
-kernel sources are the ones that were profiled.
+(profiles/<kernel>__grid3d_n16384.json), reported only while the kernel
+sources are the ones that were profiled.
 
 `cpu_baseline` is the FP64 oracle on the host cores for a bounded sample of
 rows of the same matrix (2 n^2 comparison terms per row).
@@ -82,7 +86,7 @@ def profile_record(record: str):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    return rec if rec.get("sources_sha256") == sources_digest() else None
+    return rec if rec.get("sources_sha256") == sources_digest(rec.get("sources", PROFILE_SOURCES)) else None
 
 
 def cpu_model() -> str:
@@ -290,7 +294,7 @@ def variants_bench(dev, reps: int = 3):
     Dg = torch.from_numpy(synth.mixture8d(n=n)).to(dev)
     out = {"workload": "mixture8d n=4096 seed 2"}
     ref = None
-    for variant in ("pairwise", "hybrid", "triplet"):
+    for variant in ("pairwise", "hybrid", "triplet", "hybrid2"):
         ws = pald.workspace(n, dev, variant=variant)
         U, C = pald.cohesion(Dg, variant=variant, ws=ws)
         torch.cuda.synchronize()
@@ -308,11 +312,14 @@ def variants_bench(dev, reps: int = 3):
             ref = (U.clone(), C.clone())
         elif variant == "hybrid":
             out["hybrid_U_C_identical_to_pairwise"] = bool(torch.equal(U, ref[0]) and torch.equal(C, ref[1]))
-        else:
+        elif variant == "triplet":
             out["triplet_U_equal"] = bool(torch.equal(U, ref[0]))
             rel = ((C.double() - ref[1].double()).abs() / ref[1].double().abs().clamp_min(1e-300))
             rel = torch.where(ref[1] == 0, (C != 0).double(), rel)
             out["triplet_vs_pairwise_max_rel"] = float(rel.max().item())
+            ref_t = C.clone()
+        else:
+            out["hybrid2_U_pairwise_C_triplet_identical"] = bool(torch.equal(U, ref[0]) and torch.equal(C, ref_t))
         del ws
     return out
 
@@ -401,7 +408,7 @@ def main():
                     help="batched: skip timing the one-launch form beside the tuned split form")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the distance front end, local depths and strong-tie measurements")
-    ap.add_argument("--variant", default="auto", choices=["auto", "pairwise", "triplet", "hybrid"],
+    ap.add_argument("--variant", default="auto", choices=["auto", "pairwise", "triplet", "hybrid", "hybrid2"],
                     help="algorithm of the timed step (default: the library's tuned choice, pairwise)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="instead of the benchmark, measure the vector issue rate of each instruction class "
@@ -450,6 +457,8 @@ def main():
     else:
         D = synth.workload(args.workload, n=n, seed=seed)
         Dg = torch.from_numpy(D).to(dev)
+    run_variant = pald.resolved_variant(n, variant=args.variant)
+    progress(f"variant: {run_variant}")
     ws = pald.workspace(n, dev, variant=args.variant)
     U = torch.empty((n, n), dtype=torch.int32, device=dev)
     C = torch.empty((n, n), dtype=torch.float32, device=dev)
@@ -478,13 +487,14 @@ def main():
 
     # per-step kernel time (a large grid runs as several launches per step)
     roofline = None
-    if "pass2_cohesion" in kt:
-        p2_ms = kt["pass2_cohesion"][0] / args.steps
-        p2_launches = kt["pass2_cohesion"][1] // args.steps
+    p2_kind = next((k for k in ("pass2_cohesion", "triplet_pass2") if k in kt), None)
+    if p2_kind:
+        p2_ms = kt[p2_kind][0] / args.steps
+        p2_launches = kt[p2_kind][1] // args.steps
         terms = n * n * (n - 1)
         p2_achieved = PASS2_OPS_PER_TERM * terms / (p2_ms / 1e3) / 1e12
         cmp_achieved = PASS2_COMPARES_PER_TERM * terms / (p2_ms / 1e3) / 1e12
-        rec = profile_record("pass2_cohesion__grid3d_n16384.json") if (n, args.workload) == (N, "grid3d") else None
+        rec = profile_record(f"{p2_kind}__grid3d_n16384.json") if (n, args.workload) == (N, "grid3d") else None
         issued = rec["valu_insts"] * 64 / terms if rec else None
         roofline = {
             "bound": "alu",
@@ -493,7 +503,7 @@ def main():
             "unit": "T VALU lane-ops/s",
             "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
             "traffic": rec["traffic_bytes"] if rec else None,
-            "kernel": "pass2_cohesion",
+            "kernel": p2_kind,
             "kernel_ms": round(p2_ms, 3),
             "launches_per_step": p2_launches,
             "ops_per_term": PASS2_OPS_PER_TERM,
@@ -578,7 +588,10 @@ def main():
                               "uniform2d": "uniform in [0,1]^2"}[args.workload],
                    "distance": "squared euclidean (integer, fp32)" if args.workload == "grid3d"
                    else "euclidean (fp32)",
-                   "accumulation": "fp32 runs + Kahan partials, fp64 final reduce"},
+                   "variant": run_variant,
+                   "accumulation": "fp32 runs + Kahan partials, "
+                   + ("64-bit fixed-point cross-tile sums" if run_variant in ("triplet", "hybrid2")
+                      else "fp64 final reduce")},
         "roofline": roofline,
         "cpu_baseline": base,
         "kernels_ms": kernels,

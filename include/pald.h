@@ -73,10 +73,15 @@ enum {
                                   (x,y) tiles for U, (x,z) tiles for C */
     PALD_VARIANT_TRIPLET = 2,  /* Section 3 triplet algorithm: one visit per
                                   unordered triple, shared comparisons */
-    PALD_VARIANT_HYBRID = 3    /* triplet pass 1 + pairwise pass 2, the mix the
+    PALD_VARIANT_HYBRID = 3,   /* triplet pass 1 + pairwise pass 2, the mix the
                                   appendix's per-pass breakdown suggests; U and
                                   C equal the pairwise variant's bit for bit;
                                   y_chunks applies, z_chunks must be 0 */
+    PALD_VARIANT_HYBRID2 = 4   /* pairwise pass 1 + triplet pass 2, the faster
+                                  pass of each on this GPU; U equals the pairwise
+                                  variant's and C the triplet variant's bit for
+                                  bit; z_chunks applies, y_chunks must be 0,
+                                  compensated accumulation only */
 };
 
 /* Accumulation of the cohesion sums. */
@@ -108,6 +113,14 @@ int32_t pald_version(void);
  * options `opt` (NULL = defaults).  Returns 0 if n < 2 or opt is invalid. */
 size_t pald_workspace_bytes(int64_t n, const pald_options *opt);
 
+/* The variant (PALD_VARIANT_PAIRWISE .. PALD_VARIANT_HYBRID2) that
+ * pald_cohesion runs for an n x n problem with options `opt` (NULL =
+ * defaults): the given one, or for PALD_VARIANT_AUTO the library's built-in
+ * tuned choice for n (the autotuner's per-size table), falling back to the
+ * pairwise variant where that choice does not take the other options.
+ * Returns -1 if opt is invalid. */
+int32_t pald_resolved_variant(int64_t n, const pald_options *opt);
+
 /*
  * Pass 1 only: the local focus sizes U (Section 2 definition, the first loop
  * of the pairwise algorithm in Section 3).  Needs no workspace.
@@ -130,8 +143,8 @@ pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd,
  *        contents on entry are ignored and on exit unspecified
  * Errors: PALD_ERR_ARG for null D/C/ws, n < 2, a leading dimension < n, small
  * ws; PALD_ERR_UNSUPPORTED for an unknown variant/accum or nonzero reserved,
- * and for the triplet variant above n = 2^18 (its 64-bit fixed-point sums are
- * exact up to there).
+ * and for the triplet and second hybrid variants above n = 2^18 (the 64-bit
+ * fixed-point sums of their pass 2 are exact up to there).
  */
 pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd,
                           int32_t *U, int64_t ldu,

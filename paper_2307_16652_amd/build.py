@@ -51,7 +51,7 @@ PROBE_LIB = os.path.join(PKG, "libpald_probe.so")
 TUNING = os.path.join(PKG, "tuning")
 TUNED_HEADER = os.path.join(CSRC, "tuned_gfx950.h")
 _VARIANT_ENUM = {"pairwise": "PALD_VARIANT_PAIRWISE", "triplet": "PALD_VARIANT_TRIPLET",
-                 "hybrid": "PALD_VARIANT_HYBRID"}
+                 "hybrid": "PALD_VARIANT_HYBRID", "hybrid2": "PALD_VARIANT_HYBRID2"}
 
 
 def tuned_header_text() -> str:

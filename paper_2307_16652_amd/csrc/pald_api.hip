@@ -85,7 +85,7 @@ pald_status read_opts(const pald_options *o, Opts &out) {
     if (!o) return PALD_OK;
     for (int r : o->reserved)
         if (r != 0) return PALD_ERR_UNSUPPORTED;
-    if (o->variant < PALD_VARIANT_AUTO || o->variant > PALD_VARIANT_HYBRID) return PALD_ERR_UNSUPPORTED;
+    if (o->variant < PALD_VARIANT_AUTO || o->variant > PALD_VARIANT_HYBRID2) return PALD_ERR_UNSUPPORTED;
     if (o->accum != PALD_ACC_COMPENSATED && o->accum != PALD_ACC_F64) return PALD_ERR_UNSUPPORTED;
     if (o->y_chunks < 0 || o->z_chunks < 0) return PALD_ERR_ARG;
     if (o->flags & ~PALD_FLAG_TIMING) return PALD_ERR_UNSUPPORTED;
@@ -108,6 +108,9 @@ void resolve_variant(int64_t n, Opts &o) {
     if (v == PALD_VARIANT_TRIPLET && (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0))
         v = PALD_VARIANT_PAIRWISE;
     if (v == PALD_VARIANT_HYBRID && o.z_chunks != 0) v = PALD_VARIANT_PAIRWISE;
+    if (v == PALD_VARIANT_HYBRID2 && (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0)) v = PALD_VARIANT_PAIRWISE;
+    // the triplet pass 2's fixed-point sums are exact up to 2^18 points
+    if ((v == PALD_VARIANT_TRIPLET || v == PALD_VARIANT_HYBRID2) && n > ((int64_t)1 << 18)) v = PALD_VARIANT_PAIRWISE;
     o.variant = v;
 }
 
@@ -295,8 +298,11 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     return launch_status();
 }
 
+// The triplet pass 2 (PALD_VARIANT_TRIPLET: after the triplet pass 1;
+// PALD_VARIANT_HYBRID2: after the pairwise pass 1 of options o).
 pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, float *C, int64_t ldc,
-                             void *ws, size_t ws_bytes, hipStream_t s, bool timing) {
+                             void *ws, size_t ws_bytes, hipStream_t s, const Opts &o) {
+    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
     if (n > ((int64_t)1 << 18)) return PALD_ERR_UNSUPPORTED;  // the fixed-point sums are exact up to 2^18 points
     const TripletPlan t = triplet_plan(n);
     if (ws_bytes < t.bytes) return PALD_ERR_ARG;
@@ -311,10 +317,19 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
         Ub = reinterpret_cast<int32_t *>(base + t.off_u);
         ldub = n;
     }
-    if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(n, 256), 64);
-    weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, t.ldw, n);
-    if (pald_status st = launch_status(); st != PALD_OK) return st;
+    if (o.variant == PALD_VARIANT_HYBRID2) {
+        Opts o1 = o;
+        o1.variant = PALD_VARIANT_PAIRWISE;
+        Plan p1;
+        if (pald_status st = make_plan(n, o1, p1); st != PALD_OK) return st;
+        if (p1.ldw != t.ldw) return PALD_ERR_UNSUPPORTED;  // both lay W out with rows padded to 64
+        if (pald_status st = run_pass1(D, n, ldd, Ub, ldub, W, t.ldw, p1, s, timing); st != PALD_OK) return st;
+    } else {
+        if (pald_status st = triplet_focus(D, n, ldd, Ub, ldub, s, timing); st != PALD_OK) return st;
+        weights_kernel<<<dim3(gx, rows_grid(n)), 256, 0, s>>>(Ub, ldub, W, t.ldw, n);
+        if (pald_status st = launch_status(); st != PALD_OK) return st;
+    }
     triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A, B, scale);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
@@ -479,10 +494,17 @@ size_t pald_workspace_bytes(int64_t n, const pald_options *opt) {
     Opts o;
     if (n < 2 || read_opts(opt, o) != PALD_OK) return 0;
     resolve_variant(n, o);
-    if (o.variant == PALD_VARIANT_TRIPLET) return triplet_workspace_bytes(n);
+    if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID2) return triplet_workspace_bytes(n);
     Plan p;
     if (make_plan(n, o, p) != PALD_OK) return 0;
     return p.bytes;
+}
+
+int32_t pald_resolved_variant(int64_t n, const pald_options *opt) {
+    Opts o;
+    if (read_opts(opt, o) != PALD_OK) return -1;
+    resolve_variant(n, o);
+    return o.variant;
 }
 
 pald_status pald_focus_sizes(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, void *stream,
@@ -506,10 +528,10 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     if ((reinterpret_cast<uintptr_t>(ws) & (ALIGN - 1)) != 0) return PALD_ERR_ARG;
     resolve_variant(n, o);
     hipStream_t s = (hipStream_t)stream;
-    const bool timing = (o.flags & PALD_FLAG_TIMING) != 0;
-    if (o.variant == PALD_VARIANT_TRIPLET) {
-        if (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
-        return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, timing);
+    if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID2) {
+        if (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0) return PALD_ERR_UNSUPPORTED;
+        if (o.variant == PALD_VARIANT_TRIPLET && o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
+        return triplet_cohesion(D, n, ldd, U, U ? ldu : 0, C, ldc, ws, ws_bytes, s, o);
     }
     if (o.variant == PALD_VARIANT_HYBRID && o.z_chunks != 0) return PALD_ERR_UNSUPPORTED;
     Plan p;
@@ -523,7 +545,7 @@ pald_status pald_cohesion_noalloc(const float *D, int64_t n, int64_t ldd, int32_
     Opts o;
     if (pald_status st = read_opts(opt, o); st != PALD_OK) return st;
     if (!D || !C || n < 2 || ldd < n || ldc < n || (U && ldu < n)) return PALD_ERR_ARG;
-    if (o.variant == PALD_VARIANT_TRIPLET || o.variant == PALD_VARIANT_HYBRID) return PALD_ERR_UNSUPPORTED;
+    if (o.variant != PALD_VARIANT_AUTO && o.variant != PALD_VARIANT_PAIRWISE) return PALD_ERR_UNSUPPORTED;
     o.variant = PALD_VARIANT_PAIRWISE;  // AUTO runs pairwise here
     Plan p;
     if (pald_status st = make_plan(n, o, p); st != PALD_OK) return st;

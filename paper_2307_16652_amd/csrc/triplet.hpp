@@ -60,7 +60,7 @@ constexpr int TRI_T = 64;         // owner tile side
 constexpr int TRI_R = 4;          // 4 x 4 (p, r) per thread
 constexpr int TRI_KQ = 8;         // q rows per LDS stage
 constexpr int TRI_THREADS = 256;  // tid = tx * 16 + tz; p = X0 + 4 tx + i, r = Z0 + 4 tz + j
-constexpr int TRI_RUN = 4;        // q values per float32 run of the (p, r) sums (at most 8 half weights)
+constexpr int TRI_RUN = 8;        // q values per float32 run of the (p, r) sums (one term each)
 // workgroups per CU each pass is compiled for (its register budget)
 #ifndef PALD_TRI_MIN_BLOCKS1
 #define PALD_TRI_MIN_BLOCKS1 4
@@ -244,13 +244,14 @@ __device__ __forceinline__ unsigned long long fixed_of(float v, int32_t fbits) {
 // (the thread's r_0..r_3), registers only.  a = key d_pq, b = key d_pr,
 // c = key d_qr; m = min(a, b, c), e_a = [a == m], e_b = [b == m], e_c =
 // [c == m], computed with EXEC = the lanes whose triple is valid, so that the
-// masks are 0 elsewhere.  Then EXEC takes each mask in turn and the terms are
-// added as half weights (once under e, once more under e minus the tie):
+// masks are 0 elsewhere.  Then EXEC takes each mask in turn:
 //   pass 1: u_pq += e_b | e_c, u_pr += e_a | e_c, u_qr += e_a | e_b
 //           (counts in float32, exact below 2^24);
-//   pass 2: c_pq += W_pr/2 (e_a, e_a & ~e_c),  c_qp += W_qr/2 (e_a, e_a & ~e_b),
-//           c_pr += W_pq/2 (e_b, e_b & ~e_c),  c_rp += W_qr/2 (e_b, e_b & ~e_a),
-//           c_qr += W_pq/2 (e_c, e_c & ~e_b),  c_rq += W_pr/2 (e_c, e_c & ~e_a).
+//   pass 2, with f_x = 2 - [e_x]:
+//           under e_a: c_pq += W_pr/2 f_c, c_qp += W_qr/2 f_b;
+//           under e_b: c_pr += W_pq/2 f_c, c_rp += W_qr/2 f_a;
+//           under e_c: c_qr += W_pq/2 f_b, c_rq += W_pr/2 f_a
+//           (a full weight without a tie, half of it on a tie).
 // The last instruction restores EXEC to `full`; the s_nop keeps the lane
 // permutations that read the sums clear of the last writes.
 #define PALD_T_CMP(k, e)                                                                                         \
@@ -266,29 +267,27 @@ __device__ __forceinline__ unsigned long long fixed_of(float v, int32_t fbits) {
     "v_add_f32 %[rf" #k "], 1.0, %[rf" #k "]\n\t"                                                             \
     "s_or_b64 exec, %[ea" #e "], %[eb" #e "]\n\t"                                                             \
     "v_add_f32 %[tqr" #k "], 1.0, %[tqr" #k "]\n\t"
-#define PALD_T_C(k, e)                                                                                              \
+// Pass 2 adds each term with one multiply-add: under EXEC = e_a, c_pq +=
+// W_pr/2 f_c and c_qp += W_qr/2 f_b, and so on, with f_x = 2 - [e_x] (1 on a
+// tie with x, else 2) from a select; the products are exact, so each term is
+// one rounding, as an add.
+#define PALD_T_CMPF(k, e)                                                                                        \
+    PALD_T_CMP(k, e)                                                                                             \
+    "v_cndmask_b32_e64 %[fa" #e "], 2.0, 1.0, %[ea" #e "]\n\t"                                                \
+    "v_cndmask_b32_e64 %[fb" #e "], 2.0, 1.0, %[eb" #e "]\n\t"                                                \
+    "v_cndmask_b32_e64 %[fc" #e "], 2.0, 1.0, %[ec" #e "]\n\t"
+#define PALD_T_F(k, e)                                                                                           \
     "s_mov_b64 exec, %[ea" #e "]\n\t"                                                                         \
-    "v_add_f32 %[tpq], %[tpq], %[hpr" #k "]\n\t"                                                              \
-    "v_add_f32 %[tqp], %[tqp], %[hc" #k "]\n\t"                                                               \
-    "s_andn2_b64 exec, %[ea" #e "], %[ec" #e "]\n\t"                                                          \
-    "v_add_f32 %[tpq], %[tpq], %[hpr" #k "]\n\t"                                                              \
-    "s_andn2_b64 exec, %[ea" #e "], %[eb" #e "]\n\t"                                                          \
-    "v_add_f32 %[tqp], %[tqp], %[hc" #k "]\n\t"                                                               \
+    "v_fmac_f32 %[tpq], %[hpr" #k "], %[fc" #e "]\n\t"                                                        \
+    "v_fmac_f32 %[tqp], %[hc" #k "], %[fb" #e "]\n\t"                                                         \
     "s_mov_b64 exec, %[eb" #e "]\n\t"                                                                         \
-    "v_add_f32 %[rf" #k "], %[rf" #k "], %[ha]\n\t"                                                           \
-    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hc" #k "]\n\t"                                                     \
-    "s_andn2_b64 exec, %[eb" #e "], %[ec" #e "]\n\t"                                                          \
-    "v_add_f32 %[rf" #k "], %[rf" #k "], %[ha]\n\t"                                                           \
-    "s_andn2_b64 exec, %[eb" #e "], %[ea" #e "]\n\t"                                                          \
-    "v_add_f32 %[rr" #k "], %[rr" #k "], %[hc" #k "]\n\t"                                                     \
+    "v_fmac_f32 %[rf" #k "], %[ha], %[fc" #e "]\n\t"                                                          \
+    "v_fmac_f32 %[rr" #k "], %[hc" #k "], %[fa" #e "]\n\t"                                                    \
     "s_mov_b64 exec, %[ec" #e "]\n\t"                                                                         \
-    "v_add_f32 %[tqr" #k "], %[tqr" #k "], %[ha]\n\t"                                                         \
-    "v_add_f32 %[trq" #k "], %[trq" #k "], %[hpr" #k "]\n\t"                                                  \
-    "s_andn2_b64 exec, %[ec" #e "], %[eb" #e "]\n\t"                                                          \
-    "v_add_f32 %[tqr" #k "], %[tqr" #k "], %[ha]\n\t"                                                         \
-    "s_andn2_b64 exec, %[ec" #e "], %[ea" #e "]\n\t"                                                          \
-    "v_add_f32 %[trq" #k "], %[trq" #k "], %[hpr" #k "]\n\t"
+    "v_fmac_f32 %[tqr" #k "], %[ha], %[fb" #e "]\n\t"                                                         \
+    "v_fmac_f32 %[trq" #k "], %[hpr" #k "], %[fa" #e "]\n\t"
 #define PALD_T_MASKS(e) [ea##e] "=&s"(ea[e]), [eb##e] "=&s"(eb[e]), [ec##e] "=&s"(ec[e])
+#define PALD_T_FS(e) [fa##e] "=&v"(fa[e]), [fb##e] "=&v"(fb[e]), [fc##e] "=&v"(fc[e])
 #define PALD_T_IN(k) [b##k] "v"(b[k]), [c##k] "v"(c[k]), [vr##k] "s"(vr[k])
 #define PALD_T_IN2(k) [hpr##k] "v"(hpr[k]), [hc##k] "v"(hc[k])
 
@@ -316,23 +315,27 @@ __device__ __forceinline__ void triplet_cohesion4(float &tpq, float &tqp, float 
                                                   const uint64_t (&vr)[4], uint64_t full) {
     uint64_t ea[2], eb[2], ec[2];
     uint32_t m;
-    asm volatile(PALD_T_CMP(0, 0) PALD_T_CMP(1, 1) PALD_T_C(0, 0) PALD_T_CMP(2, 0) PALD_T_C(1, 1)
-                 PALD_T_CMP(3, 1) PALD_T_C(2, 0) PALD_T_C(3, 1)
+    float fa[2], fb[2], fc[2];
+    asm volatile(PALD_T_CMPF(0, 0) PALD_T_CMPF(1, 1) PALD_T_F(0, 0) PALD_T_CMPF(2, 0) PALD_T_F(1, 1)
+                 PALD_T_CMPF(3, 1) PALD_T_F(2, 0) PALD_T_F(3, 1)
                  "s_mov_b64 exec, %[full]\n\t"
                  "s_nop 4"
                  : [tpq] "+v"(tpq), [tqp] "+v"(tqp), [rf0] "+v"(rf[0]), [rf1] "+v"(rf[1]), [rf2] "+v"(rf[2]),
                    [rf3] "+v"(rf[3]), [rr0] "+v"(rr[0]), [rr1] "+v"(rr[1]), [rr2] "+v"(rr[2]), [rr3] "+v"(rr[3]),
                    [tqr0] "+v"(tqr[0]), [tqr1] "+v"(tqr[1]), [tqr2] "+v"(tqr[2]), [tqr3] "+v"(tqr[3]),
                    [trq0] "+v"(trq[0]), [trq1] "+v"(trq[1]), [trq2] "+v"(trq[2]), [trq3] "+v"(trq[3]),
-                   [m] "=&v"(m), PALD_T_MASKS(0), PALD_T_MASKS(1)
+                   [m] "=&v"(m), PALD_T_MASKS(0), PALD_T_MASKS(1), PALD_T_FS(0), PALD_T_FS(1)
                  : [a] "v"(a), [ha] "v"(ha), [vp] "s"(vp), [full] "s"(full), PALD_T_IN(0), PALD_T_IN(1),
                    PALD_T_IN(2), PALD_T_IN(3), PALD_T_IN2(0), PALD_T_IN2(1), PALD_T_IN2(2), PALD_T_IN2(3)
                  : "scc");
+
 }
 #undef PALD_T_CMP
 #undef PALD_T_U
-#undef PALD_T_C
 #undef PALD_T_MASKS
+#undef PALD_T_CMPF
+#undef PALD_T_F
+#undef PALD_T_FS
 #undef PALD_T_IN
 #undef PALD_T_IN2
 
@@ -479,11 +482,11 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
                 const float hav[R] = {ha4.x, ha4.y, ha4.z, ha4.w};
                 const float hcv[R] = {hc4.x, hc4.y, hc4.z, hc4.w};
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    tpq[i] = tqp[i] = 0.0f;
-                    triplet_cohesion4(tpq[i], tqp[i], rf[i], rr[i], tqr, trq, av[i], hav[i], b[i], hpr[i], cv, hcv,
-                                      vp[i], vr, full);
-                }
+                    for (int i = 0; i < R; ++i) {
+                        tpq[i] = tqp[i] = 0.0f;
+                        triplet_cohesion4(tpq[i], tqp[i], rf[i], rr[i], tqr, trq, av[i], hav[i], b[i], hpr[i], cv,
+                                          hcv, vp[i], vr, full);
+                    }
             } else {
 #pragma unroll
                 for (int i = 0; i < R; ++i) {

@@ -32,7 +32,9 @@ constexpr VariantPick kVariants[] = {
     {512, PALD_VARIANT_PAIRWISE},
     {1024, PALD_VARIANT_PAIRWISE},
     {2048, PALD_VARIANT_PAIRWISE},
-    {4096, PALD_VARIANT_PAIRWISE},
-    {8192, PALD_VARIANT_PAIRWISE}};
+    {4096, PALD_VARIANT_HYBRID2},
+    {8192, PALD_VARIANT_HYBRID2},
+    {16384, PALD_VARIANT_HYBRID2},
+    {32768, PALD_VARIANT_PAIRWISE}};
 
 }  // namespace pald_tuned

@@ -18,7 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libpald.so")
 
 OK, ERR_ARG, ERR_INPUT, ERR_DEVICE, ERR_NOMEM, ERR_UNSUPPORTED = range(6)
-VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2, "hybrid": 3}
+VARIANTS = {"auto": 0, "pairwise": 1, "triplet": 2, "hybrid": 3, "hybrid2": 4}
 ACCUMS = {"compensated": 0, "f64": 1}
 FLAG_TIMING = 1
 TIMING_KINDS = ("pass1_focus", "weights", "pass2_cohesion", "finalize", "batched",
@@ -39,6 +39,7 @@ EXPORTED = (
     "pald_timings_collect", "pald_distances", "pald_local_depths", "pald_strong_ties",
     "pald_graph_distances_workspace_bytes", "pald_graph_distances", "pald_cohesion_noalloc",
     "pald_rows_workspace_bytes", "pald_cohesion_rows", "pald_ooc_workspace_bytes", "pald_cohesion_ooc",
+    "pald_resolved_variant",
 )
 BATCH_MAX_BUCKETS = 8
 BATCH_TIMESTAMPS = 1
@@ -144,6 +145,8 @@ def load_library(path: str | None = None):
     lib.pald_version.restype = i32
     lib.pald_workspace_bytes.argtypes = [i64, opt]
     lib.pald_workspace_bytes.restype = sz
+    lib.pald_resolved_variant.argtypes = [i64, opt]
+    lib.pald_resolved_variant.restype = i32
     lib.pald_focus_sizes.argtypes = [vp, i64, i64, vp, i64, vp, opt]
     lib.pald_focus_sizes.restype = i32
     lib.pald_cohesion.argtypes = [vp, i64, i64, vp, i64, vp, i64, vp, sz, vp, opt]
@@ -257,6 +260,15 @@ def _check_matrix(D):
 def workspace_bytes(n: int, **opts) -> int:
     o = make_options(**opts)
     return int(load_library().pald_workspace_bytes(int(n), ctypes.byref(o)))
+
+
+def resolved_variant(n: int, **opts) -> str:
+    """The variant pald_cohesion runs for size n with these options ("auto" resolved)."""
+    v = int(load_library().pald_resolved_variant(int(n), ctypes.byref(make_options(**opts))))
+    names = {i: k for k, i in VARIANTS.items()}
+    if v not in names or v == 0:
+        raise PaldError(ERR_UNSUPPORTED, "pald_resolved_variant")
+    return names[v]
 
 
 def workspace(n: int, device, **opts):

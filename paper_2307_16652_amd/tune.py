@@ -26,8 +26,9 @@ Both tile shapes are compiled into the batched kernel; the search picks one
 per bucket.
 
 With --variants it instead times the pairwise, hybrid (triplet pass 1 +
-pairwise pass 2) and triplet variants of the single-matrix path on Gaussian
-mixtures of several sizes and writes, per size, the fastest one to
+pairwise pass 2), triplet and hybrid2 (pairwise pass 1 + triplet pass 2)
+variants of the single-matrix path on Gaussian mixtures of several sizes and
+writes, per size, the fastest one to
 tuning/variants_gfx950.json, which the next build compiles into the library's
 PALD_VARIANT_AUTO choice.
 """
@@ -84,7 +85,7 @@ class Batch:
             elif not torch.equal(U, self.ref[0]) or not torch.allclose(C, self.ref[1], rtol=2e-6, atol=0):
                 raise RuntimeError("a tuning candidate changed the results")
             times = []
-            for _ in range(reps):
+            for _ in range(reps if n <= 16384 else 1):  # seconds per call above that
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
@@ -163,7 +164,7 @@ def tune(reps: int = 3, out: str | None = None) -> dict:
     return result
 
 
-VARIANT_SIZES = (256, 512, 1024, 2048, 4096, 8192)
+VARIANT_SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384, 32768)
 
 
 def tune_variants(reps: int = 3, out: str | None = None) -> dict:
@@ -177,12 +178,12 @@ def tune_variants(reps: int = 3, out: str | None = None) -> dict:
     for n in VARIANT_SIZES:
         Dg = torch.from_numpy(synth.mixture8d(n=n, seed=2)).to(dev)
         ms = {}
-        for variant in ("pairwise", "hybrid", "triplet"):
+        for variant in ("pairwise", "hybrid", "triplet", "hybrid2"):
             ws = pald.workspace(n, dev, variant=variant)
             U, C = pald.cohesion(Dg, variant=variant, ws=ws)
             torch.cuda.synchronize()
             times = []
-            for _ in range(reps):
+            for _ in range(reps if n <= 16384 else 1):  # seconds per call above that
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()

@@ -58,6 +58,17 @@ def test_auto_variant_follows_the_tuned_table():
             if size <= n:
                 pick = v
         assert pald.workspace_bytes(n, variant="auto") == pald.workspace_bytes(n, variant=pick), n
+    for n in (100, 256, 300, 1024, 5000, 20000):
+        pick = table[0][1]
+        for size, v in table:
+            if size <= n:
+                pick = v
+        assert pald.resolved_variant(n) == pick, n
+        assert pald.resolved_variant(n, variant="triplet") == "triplet"
+    assert pald.load_library().pald_resolved_variant(100, ctypes.byref(pald.make_options(accum="f64"))) in (1, 3)
+    bad = pald.make_options()
+    bad.variant = 9
+    assert pald.load_library().pald_resolved_variant(100, ctypes.byref(bad)) == -1
     # the triplet variant takes no forced split: AUTO with one runs pairwise
     assert pald.workspace_bytes(3000, variant="auto", y_chunks=2) == \
         pald.workspace_bytes(3000, variant="pairwise", y_chunks=2)
@@ -103,10 +114,23 @@ def test_unknown_options_rejected():
     o = pald.make_options()
     o.flags = 0x80
     assert lib.pald_focus_sizes(fake, 8, 8, fake, 8, None, ctypes.byref(o)) == pald.ERR_UNSUPPORTED
-    # the triplet variant's fixed-point sums are exact up to n = 2^18 only
+    # the triplet pass 2's fixed-point sums are exact up to n = 2^18 only
     big = (1 << 18) + 1
-    assert lib.pald_cohesion(fake, big, big, None, 0, fake, big, fake, 1 << 62, None,
-                             _opts(variant="triplet")) == pald.ERR_UNSUPPORTED
+    for v in ("triplet", "hybrid2"):
+        assert lib.pald_cohesion(fake, big, big, None, 0, fake, big, fake, 1 << 62, None,
+                                 _opts(variant=v)) == pald.ERR_UNSUPPORTED
+    # hybrid2: the triplet pass 2 takes no y split and no float64 form; the triplet
+    # variant takes no z split either
+    for kw in (dict(variant="hybrid2", y_chunks=2), dict(variant="hybrid2", accum="f64"),
+               dict(variant="triplet", z_chunks=2)):
+        assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, fake, 1 << 20, None, _opts(**kw)) == \
+            pald.ERR_UNSUPPORTED, kw
+    o = pald.make_options()
+    o.variant = 5
+    assert lib.pald_cohesion(fake, 8, 8, None, 0, fake, 8, fake, 1 << 20, None, ctypes.byref(o)) == \
+        pald.ERR_UNSUPPORTED
+    # hybrid2 needs the triplet workspace (A, B, W and U scratch)
+    assert pald.workspace_bytes(1000, variant="hybrid2") == pald.workspace_bytes(1000, variant="triplet")
     o = pald.make_options()
     o.y_chunks = -1
     assert lib.pald_workspace_bytes(8, ctypes.byref(o)) == 0

@@ -1,5 +1,8 @@
-"""The hybrid variant (triplet pass 1 + pairwise pass 2): parity with the oracle,
-and U and C bit-identical to the pairwise variant (same integers, same pass 2)."""
+"""The hybrid variants.  hybrid (triplet pass 1 + pairwise pass 2): parity with
+the oracle, and U and C bit-identical to the pairwise variant (same integers,
+same pass 2).  hybrid2 (pairwise pass 1 + triplet pass 2): parity with the
+oracle, U bit-identical to the pairwise variant's and C to the triplet
+variant's (same weights, same pass 2)."""
 import numpy as np
 import pytest
 
@@ -66,4 +69,45 @@ def test_hybrid_mixture8d_n4096_sampled():
     Uo, Co = oracle.pald_rows(D, rows)
     assert_u_equal(U[rows], Uo, "hybrid n=4096")
     err = assert_c_close(C[rows], Co, what="hybrid n=4096")
+    log(f"  max rel err {err:.3e}")
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 65, 129, 257, 300])
+def test_hybrid2_parity_and_identity(n):
+    D = synth.grid3d(n=n, seed=n) if n % 2 else synth.mixture8d(n=n, seed=n)
+    log(f"[hybrid2] n={n}")
+    U, C = gpu_cohesion(D, variant="hybrid2")
+    Uo, Co = oracle.pald(D)
+    assert_u_equal(U, Uo, f"hybrid2 n={n}")
+    assert_c_close(C, Co, what=f"hybrid2 n={n}")
+    Up, _ = gpu_cohesion(D, variant="pairwise")
+    _, Ct = gpu_cohesion(D, variant="triplet")
+    assert np.array_equal(U, Up)
+    assert np.array_equal(C.view(np.int32), Ct.view(np.int32))
+
+
+@pytest.mark.parametrize("z_chunks", [0, 3])
+def test_hybrid2_z_split_and_no_u(z_chunks):
+    import torch
+
+    from paper_2307_16652_amd import pald
+
+    D = synth.random_tie_matrix(200, (0.0, 1.0, 2.0), seed=5)
+    Uo, Co = oracle.pald(D)
+    U, C = pald.cohesion(to_gpu(D), variant="hybrid2", z_chunks=z_chunks, want_u=False)
+    torch.cuda.synchronize()
+    assert U is None
+    assert_c_close(C.cpu().numpy(), Co, what=f"hybrid2 z_chunks={z_chunks}")
+    with pytest.raises(pald.PaldError) as e:
+        pald.cohesion(to_gpu(D), variant="hybrid2", y_chunks=2)
+    assert e.value.status == pald.ERR_UNSUPPORTED
+
+
+def test_hybrid2_mixture8d_n4096_sampled():
+    D = synth.mixture8d()
+    rows = np.sort(np.random.default_rng(7).choice(4096, size=24, replace=False))
+    U, C = gpu_cohesion(D, variant="hybrid2")
+    Uo, Co = oracle.pald_rows(D, rows)
+    assert_u_equal(U[rows], Uo, "hybrid2 n=4096")
+    err = assert_c_close(C[rows], Co, what="hybrid2 n=4096")
     log(f"  max rel err {err:.3e}")

@@ -242,11 +242,12 @@ def test_config_mixture8d_n4096_full():
 
     D = synth.mixture8d()
     log("[parity] mixture8d n=4096 (full oracle)")
-    U, C = gpu_cohesion(D)
     Uo, Co = oracle_full_cached("mixture8d_4096", D)
-    assert_u_equal(U, Uo, "mixture8d n=4096")
-    err = assert_c_close(C, Co, what="mixture8d n=4096")
-    check_invariants(U, C, "mixture8d")
+    for variant in ("auto", "pairwise"):  # auto: the tuned choice at this size
+        U, C = gpu_cohesion(D, variant=variant)
+        assert_u_equal(U, Uo, f"mixture8d n=4096 {variant}")
+        err = assert_c_close(C, Co, what=f"mixture8d n=4096 {variant}")
+        check_invariants(U, C, "mixture8d")
     _, C64 = gpu_cohesion(D, accum="f64")
     err64 = assert_c_close(C64, Co, what="mixture8d n=4096, FP64 form")
     log(f"  max rel err {err:.3e} (compensated), {err64:.3e} (FP64 form)")
@@ -259,19 +260,37 @@ def grid3d_oracle_rows(n: int = 16384, k: int = 256):
     return np.unique(np.concatenate([[0, n - 1], rows]))
 
 
-def test_config_grid3d_n16384_sampled():
-    """The benchmark's workload and launch configuration against the oracle on the
-    config's 256 seeded rows (plus the first and last), for the compensated and
-    the FP64-accumulate forms."""
-    D = synth.grid3d()
-    rows = grid3d_oracle_rows()
-    log(f"[parity] grid3d n=16384: oracle on {rows.size} rows")
-    Uo, Co = oracle.pald_rows(D, rows)
-    U, C = gpu_cohesion(D)
-    assert_u_equal(U[rows], Uo, "grid3d n=16384 U rows")
-    err = assert_c_close(C[rows], Co, what="grid3d n=16384 C rows")
+_GRID3D_ROWS = {}
+
+
+def grid3d_oracle_cached():
+    """(D, rows, U rows, C rows) of the n = 16384 workload, the oracle run once."""
+    if not _GRID3D_ROWS:
+        D = synth.grid3d()
+        rows = grid3d_oracle_rows()
+        log(f"[parity] grid3d n=16384: oracle on {rows.size} rows")
+        Uo, Co = oracle.pald_rows(D, rows)
+        _GRID3D_ROWS.update(D=D, rows=rows, Uo=Uo, Co=Co)
+    g = _GRID3D_ROWS
+    return g["D"], g["rows"], g["Uo"], g["Co"]
+
+
+@pytest.mark.parametrize("variant", ["pairwise", "hybrid2"])
+def test_config_grid3d_n16384_sampled(variant):
+    """The benchmark's workload against the oracle on the config's 256 seeded rows
+    (plus the first and last): the pairwise variant in its compensated and
+    FP64-accumulate forms, and the variant the tuned table runs at this size
+    (pairwise pass 1 + triplet pass 2)."""
+    D, rows, Uo, Co = grid3d_oracle_cached()
+    log(f"[parity] grid3d n=16384 {variant}")
+    U, C = gpu_cohesion(D, variant=variant)
+    assert_u_equal(U[rows], Uo, f"grid3d n=16384 {variant} U rows")
+    err = assert_c_close(C[rows], Co, what=f"grid3d n=16384 {variant} C rows")
     check_invariants(U, C, "grid3d")
     del U, C
+    if variant != "pairwise":
+        log(f"  {rows.size} rows: max rel err {err:.3e}")
+        return
     U64, C64 = gpu_cohesion(D, accum="f64")
     assert_u_equal(U64[rows], Uo, "grid3d n=16384 U rows, FP64 form")
     err64 = assert_c_close(C64[rows], Co, what="grid3d n=16384 C rows, FP64 form")
@@ -297,7 +316,8 @@ def test_cohesion_captured_in_a_graph_replays_exactly():
 
     from paper_2307_16652_amd import pald
 
-    for n, opts in ((300, {}), (257, {"y_chunks": 3, "z_chunks": 2})):
+    for n, opts in ((300, {}), (257, {"y_chunks": 3, "z_chunks": 2}), (300, {"variant": "hybrid2"}),
+                    (260, {"variant": "triplet"})):
         D = to_gpu(synth.mixture8d(n=n, seed=40 + n))
         ws = pald.workspace(n, D.device, **opts)
         U = torch.empty((n, n), dtype=torch.int32, device="cuda")

@@ -127,7 +127,7 @@ def test_config_mixture8d_n4096_full():
     log(f"  max rel err {err:.3e}")
 
 
-@pytest.mark.parametrize("variant", ["triplet", "hybrid"])
+@pytest.mark.parametrize("variant", ["triplet", "hybrid", "hybrid2"])
 def test_bitwise_reproducible(variant):
     """U and C of the triplet and hybrid variants are the same bits on every run:
     their owners' partial sums are combined with integer (fixed-point) atomics,

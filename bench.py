@@ -57,6 +57,10 @@ VALU_PEAK_TOPS = 256 * 4 * 64 * (2 / 4) * 2.4e9 / 1e12  # 78.64 T lane-ops/s
 COMPARE_PEAK_TOPS = 256 * 4 * 64 * (1 / 4) * 2.4e9 / 1e12  # 39.32 T lane-ops/s
 PASS2_OPS_PER_TERM = 4
 PASS2_COMPARES_PER_TERM = 3
+# lane-ops per cohesion term of each pass-2 kernel's own block: pairwise, 4
+# compares and 4 masked adds per pair and y (2 terms); triplet, a min, 3
+# compares, 3 selects and 6 multiply-adds per triple (6 terms)
+BLOCK_OPS_PER_TERM = {"pass2_cohesion": 4.0, "triplet_pass2": round(13 / 6, 4)}
 # Pass 1 counts 64 z per instruction pair: per (pair, 64 z) one vector min +
 # one vector compare and one scalar popcount + one scalar add.  Each pipe
 # issues one wave instruction per SIMD every 4 cycles (vector: 64 lanes on
@@ -495,18 +499,21 @@ def main():
         p2_achieved = PASS2_OPS_PER_TERM * terms / (p2_ms / 1e3) / 1e12
         cmp_achieved = PASS2_COMPARES_PER_TERM * terms / (p2_ms / 1e3) / 1e12
         rec = profile_record(f"{p2_kind}__grid3d_n16384.json") if (n, args.workload) == (N, "grid3d") else None
-        issued = rec["valu_insts"] * 64 / terms if rec else None
+        # the record holds per-dispatch averages over one step's launches
+        issued = rec["valu_insts"] * p2_launches * 64 / terms if rec else None
         roofline = {
             "bound": "alu",
             "achieved": round(p2_achieved, 3),
             "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "T VALU lane-ops/s",
             "frac": round(p2_achieved / VALU_PEAK_TOPS, 4),
-            "traffic": rec["traffic_bytes"] if rec else None,
+            "traffic": rec["traffic_bytes"] * p2_launches if rec else None,
+            "traffic_unit": "bytes per step",
             "kernel": p2_kind,
             "kernel_ms": round(p2_ms, 3),
             "launches_per_step": p2_launches,
             "ops_per_term": PASS2_OPS_PER_TERM,
+            "kernel_block_lane_ops_per_term": BLOCK_OPS_PER_TERM[p2_kind],
             "issued_lane_ops_per_term": round(issued, 3) if issued else None,
             "useful_fraction": round(PASS2_OPS_PER_TERM / issued, 4) if issued else None,
             "compare_pipe": {"achieved": round(cmp_achieved, 3), "peak": round(COMPARE_PEAK_TOPS, 3),

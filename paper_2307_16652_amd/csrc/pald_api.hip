@@ -286,7 +286,7 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 5, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<false><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, nullptr, vec, 0,
+        triplet_kernel<false><<<g, tri_threads<false>(), 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, nullptr, vec, 0,
                                                          (int32_t)t0, 0, 1.0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }
@@ -336,7 +336,7 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
         ScopedTiming tm(timing, 6, s);
         const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
-        triplet_kernel<true><<<g, TRI_THREADS, 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, B, vecd, 1, (int32_t)t0,
+        triplet_kernel<true><<<g, tri_threads<true>(), 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, B, vecd, 1, (int32_t)t0,
                                                         triplet_fixed_bits(n), scale);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
     }

@@ -57,16 +57,24 @@
 namespace pald {
 
 constexpr int TRI_T = 64;         // owner tile side
-constexpr int TRI_R = 4;          // 4 x 4 (p, r) per thread
+constexpr int TRI_R = 4;          // r per thread; p per thread: tri_rp<PASS2>() (4 x 4 or 2 x 4 pairs)
 constexpr int TRI_KQ = 8;         // q rows per LDS stage
-constexpr int TRI_THREADS = 256;  // tid = tx * 16 + tz; p = X0 + 4 tx + i, r = Z0 + 4 tz + j
+// p per thread of pass 1 / pass 2 (pass 2 holds twice the registers per pair)
+#ifndef PALD_TRI_RP2
+#define PALD_TRI_RP2 2
+#endif
+template <bool PASS2>
+constexpr int tri_rp() { return PASS2 ? PALD_TRI_RP2 : 4; }
+// threads: tid = tx * 16 + tz, p = X0 + RP tx + i, r = Z0 + 4 tz + j
+template <bool PASS2>
+constexpr int tri_threads() { return 16 * 64 / tri_rp<PASS2>(); }
 constexpr int TRI_RUN = 8;        // q values per float32 run of the (p, r) sums (one term each)
 // workgroups per CU each pass is compiled for (its register budget)
 #ifndef PALD_TRI_MIN_BLOCKS1
 #define PALD_TRI_MIN_BLOCKS1 4
 #endif
 #ifndef PALD_TRI_MIN_BLOCKS2
-#define PALD_TRI_MIN_BLOCKS2 3
+#define PALD_TRI_MIN_BLOCKS2 (PALD_TRI_RP2 == 2 ? 2 : 3)
 #endif
 // U_xy = 2 above the diagonal, 0 below it (pass 1 adds into both triangles
 // and triplet_mirror_u_kernel sums them), U_xx = #{z : d_xz <= 0}.
@@ -339,6 +347,27 @@ __device__ __forceinline__ void triplet_cohesion4(float &tpq, float &tqp, float 
 #undef PALD_T_IN
 #undef PALD_T_IN2
 
+// RP consecutive 32-bit values of a staged row, and the RP sums of a row of
+// lanes into LDS.
+template <int RP, typename V>
+__device__ __forceinline__ void load_row_vals(V (&v)[RP], const V *src) {
+    if constexpr (RP == 4) {
+        const uint4 t = *reinterpret_cast<const uint4 *>(src);
+        v[0] = __builtin_bit_cast(V, t.x); v[1] = __builtin_bit_cast(V, t.y);
+        v[2] = __builtin_bit_cast(V, t.z); v[3] = __builtin_bit_cast(V, t.w);
+    } else {
+        const uint2 t = *reinterpret_cast<const uint2 *>(src);
+        v[0] = __builtin_bit_cast(V, t.x); v[1] = __builtin_bit_cast(V, t.y);
+    }
+}
+template <int RP>
+__device__ __forceinline__ void store_row_vals(float *dst, const float (&v)[RP]) {
+    if constexpr (RP == 4)
+        *reinterpret_cast<float4 *>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+    else
+        *reinterpret_cast<float2 *>(dst) = make_float2(v[0], v[1]);
+}
+
 // One owner tile of either pass.  PASS2 = false: focus sizes into U (int32,
 // atomics, upper triangle); PASS2 = true: cohesion sums into A (64-bit fixed
 // point with fbits fraction bits, atomics).
@@ -352,11 +381,12 @@ __device__ __forceinline__ void triplet_cohesion4(float &tpq, float &tqp, float 
 // waves' partials in wave order) to the global sums.  Stages whose q lie
 // between the two blocks need no index masks.
 template <bool PASS2>
-__global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TRI_MIN_BLOCKS1) void triplet_kernel(
+__global__ __launch_bounds__(tri_threads<PASS2>(), PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TRI_MIN_BLOCKS1) void triplet_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
     int32_t *__restrict__ U, int64_t ldu, unsigned long long *__restrict__ A, unsigned long long *__restrict__ B,
     int32_t vec_d, int32_t vec_w, int32_t tile0, int32_t fbits, double scale) {
-    constexpr int T = TRI_T, R = TRI_R, KQ = TRI_KQ, NT = TRI_THREADS;
+    constexpr int T = TRI_T, R = TRI_R, RP = tri_rp<PASS2>(), KQ = TRI_KQ, NT = tri_threads<PASS2>();
+    constexpr int NW = NT / 64;                  // waves
     constexpr int LROW = PASS2 ? 4 * T : 2 * T;  // per q: a | W_qp/2 | c | W_qr/2  (pass 1: a | c)
     constexpr int CSEG = PASS2 ? 2 * T : T;      // offset of c in a row
     constexpr int ND = PASS2 ? 2 : 1;            // (p, q) and (q, p); (q, r) and (r, q)
@@ -364,10 +394,11 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
     constexpr int VPT = VPC / NT;
     static_assert(VPC % NT == 0, "stage must split evenly");
     static_assert(KQ % TRI_RUN == 0, "stages hold whole runs");
-    static_assert(R == 4 && T == 64 && NT == 256, "the lane reductions assume 4 x 4 per thread, 16 x 16 threads");
+    static_assert(R == 4 && T == 64 && (RP == 4 || RP == 2) && NT == 16 * T / RP,
+                  "the lane reductions assume RP x 4 per thread, 16 lanes over r");
     __shared__ uint4 sm[2 * KQ * LROW / 4];
-    __shared__ float pbuf[KQ][ND][T];     // (p, q) sums of the stage, by p
-    __shared__ float qbuf[4][KQ][ND][T];  // per-wave (q, r) sums of the stage, by r
+    __shared__ float pbuf[KQ][ND][T];      // (p, q) sums of the stage, by p
+    __shared__ float qbuf[NW][KQ][ND][T];  // per-wave (q, r) sums of the stage, by r
 
     int32_t bx, bz;
     tri_tile_heavy_first(tile0 + (int32_t)blockIdx.x, (int32_t)((n + T - 1) / T), bx, bz);
@@ -377,13 +408,13 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
     const bool diag_owner = bx == bz;
     const uint64_t full = __builtin_amdgcn_read_exec();
 
-    auto p = [&](int i) { return X0 + tx * R + i; };
+    auto p = [&](int i) { return X0 + tx * RP + i; };
     auto r = [&](int j) { return Z0 + tz * R + j; };
     // stationary (p, r) data: keys and half weights
-    uint32_t b[R][R];
-    float hpr[R][R];
+    uint32_t b[RP][R];
+    float hpr[RP][R];
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int i = 0; i < RP; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const bool in = p(i) < n && r(j) < n;
@@ -396,9 +427,9 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
     // (p, r) accumulators: pass 1 counts in rf; pass 2 float32 runs rf (c_pr)
     // and rr (c_rp) with Kahan sums sf, sr (a run starts from the negated
     // compensation of the previous fold)
-    float rf[R][R], rr[R][R], sf[R][R], sr[R][R];
+    float rf[RP][R], rr[RP][R], sf[RP][R], sr[RP][R];
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int i = 0; i < RP; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) rf[i][j] = rr[i][j] = sf[i][j] = sr[i][j] = 0.0f;
 
@@ -456,53 +487,50 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
         for (int qq = h; qq < h + TRI_RUN; ++qq) {
             const int64_t q = qc + qq;
             const uint32_t *rowp = s + qq * LROW;
-            const uint4 a4 = *reinterpret_cast<const uint4 *>(rowp + tx * R);
+            uint32_t av[RP];
+            float hav[RP];
+            load_row_vals<RP>(av, rowp + tx * RP);
+            if (PASS2) load_row_vals<RP>(hav, reinterpret_cast<const float *>(rowp + T + tx * RP));
             const uint4 c4 = *reinterpret_cast<const uint4 *>(rowp + CSEG + tz * R);
-            const uint32_t av[R] = {a4.x, a4.y, a4.z, a4.w};
             const uint32_t cv[R] = {c4.x, c4.y, c4.z, c4.w};
-            uint64_t vp[R], vr[R];
+            uint64_t vp[RP], vr[R];
             if (interior) {
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    vp[i] = full;
-                    vr[i] = rn[i];
-                }
+                for (int i = 0; i < RP; ++i) vp[i] = full;
+#pragma unroll
+                for (int j = 0; j < R; ++j) vr[j] = rn[j];
             } else {
                 const int32_t qx = (int32_t)(q - X0), qz = (int32_t)(q - Z0);
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    vp[i] = lane_mask(tx * R + i < qx);
-                    vr[i] = lane_mask(qz < tz * R + i) & rn[i];
-                }
+                for (int i = 0; i < RP; ++i) vp[i] = lane_mask(tx * RP + i < qx);
+#pragma unroll
+                for (int j = 0; j < R; ++j) vr[j] = lane_mask(qz < tz * R + j) & rn[j];
             }
-            float tpq[R], tqp[R], tqr[R] = {0.0f, 0.0f, 0.0f, 0.0f}, trq[R] = {0.0f, 0.0f, 0.0f, 0.0f};
+            float tpq[RP], tqp[RP], tqr[R] = {0.0f, 0.0f, 0.0f, 0.0f}, trq[R] = {0.0f, 0.0f, 0.0f, 0.0f};
             if constexpr (PASS2) {
-                const float4 ha4 = *reinterpret_cast<const float4 *>(rowp + T + tx * R);
                 const float4 hc4 = *reinterpret_cast<const float4 *>(rowp + 3 * T + tz * R);
-                const float hav[R] = {ha4.x, ha4.y, ha4.z, ha4.w};
                 const float hcv[R] = {hc4.x, hc4.y, hc4.z, hc4.w};
 #pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        tpq[i] = tqp[i] = 0.0f;
-                        triplet_cohesion4(tpq[i], tqp[i], rf[i], rr[i], tqr, trq, av[i], hav[i], b[i], hpr[i], cv,
-                                          hcv, vp[i], vr, full);
-                    }
+                for (int i = 0; i < RP; ++i) {
+                    tpq[i] = tqp[i] = 0.0f;
+                    triplet_cohesion4(tpq[i], tqp[i], rf[i], rr[i], tqr, trq, av[i], hav[i], b[i], hpr[i], cv, hcv,
+                                      vp[i], vr, full);
+                }
             } else {
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
+                for (int i = 0; i < RP; ++i) {
                     tpq[i] = 0.0f;
                     triplet_count4(tpq[i], rf[i], tqr, av[i], b[i], cv, vp[i], vr, full);
                 }
             }
             // (p, q) [and (q, p)]: sums over the 16 lanes sharing p, stored by lane 0 [and 1] of the row
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
+            for (int i = 0; i < RP; ++i) {
                 tpq[i] = row_sum16(tpq[i]);
                 if (PASS2) tqp[i] = row_sum16(tqp[i]);
             }
-            if (tz == 0) *reinterpret_cast<float4 *>(&pbuf[qq][0][tx * R]) = make_float4(tpq[0], tpq[1], tpq[2], tpq[3]);
-            if (PASS2 && tz == 1)
-                *reinterpret_cast<float4 *>(&pbuf[qq][ND - 1][tx * R]) = make_float4(tqp[0], tqp[1], tqp[2], tqp[3]);
+            if (tz == 0) store_row_vals<RP>(&pbuf[qq][0][tx * RP], tpq);
+            if (PASS2 && tz == 1) store_row_vals<RP>(&pbuf[qq][ND - 1][tx * RP], tqp);
             // (q, r) [and (r, q)]: sums over the wave's 4 rows; row k keeps
             // pass 2: direction k / 2, r_j for j = 2 (k % 2) + {0, 1}; pass 1: r_k
             if constexpr (PASS2) {
@@ -518,7 +546,7 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
         }
         if constexpr (PASS2) {  // end of a run: fold it into the Kahan sums
 #pragma unroll
-            for (int i = 0; i < R; ++i)
+            for (int i = 0; i < RP; ++i)
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     float tk = sf[i][j] + rf[i][j];
@@ -540,7 +568,9 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
             if (q >= qhi) continue;
             const int64_t pp = X0 + l, rz = Z0 + l;
             const float v = pbuf[qq][d][l];
-            const float w = ((qbuf[0][qq][d][l] + qbuf[1][qq][d][l]) + qbuf[2][qq][d][l]) + qbuf[3][qq][d][l];
+            float w = qbuf[0][qq][d][l];
+#pragma unroll
+            for (int k = 1; k < NW; ++k) w += qbuf[k][qq][d][l];
             if (PASS2) {
                 // c_pq into B[q][p], c_qp into A[q][p], c_qr into A[q][r], c_rq into B[q][r]
                 if (v != 0.0f) atomicAdd(d == 0 ? &B[q * n + pp] : &A[q * n + pp], fixed_of(v, fbits));
@@ -556,7 +586,7 @@ __global__ __launch_bounds__(TRI_THREADS, PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TR
 
     // the (p, r) sums of this owner
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+    for (int i = 0; i < RP; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             if (p(i) >= n || r(j) >= n || (diag_owner && p(i) >= r(j))) continue;

@@ -119,7 +119,8 @@ def valu_probe(waves=(8, 4), iters: int = 20000) -> dict:
     lib.pald_probe_valu.restype = ctypes.c_int32
     names = ["v_add_f32", "v_fma_f32", "v_add_u32", "v_and_b32", "v_min_u32", "v_min_f32", "v_cmp_lt_u32_e64",
              "v_cmp_le_f32_e64", "v_cndmask_b32_e64", "v_addc_co_u32_e64", "v_cmp_lt_u32_e64 + v_add_f32",
-             "v_min_u32 + v_add_f32", "v_min_u32 + v_and_b32", "pass-2 block: 16 compares + 16 masked v_add_f32"]
+             "v_min_u32 + v_add_f32", "v_min_u32 + v_and_b32", "pass-2 block: 16 compares + 16 masked v_add_f32",
+             "triplet pass-2 block: 4 triples, 28 min/compare/select + 24 masked v_fmac_f32"]
     assert lib.pald_probe_classes() == len(names)
     out = {"unit": "SIMD cycles per wave64 vector instruction (at the measured shader clock)", "classes": {}}
     buf = (ctypes.c_double * 4)()

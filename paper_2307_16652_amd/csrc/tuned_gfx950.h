@@ -35,6 +35,6 @@ constexpr VariantPick kVariants[] = {
     {4096, PALD_VARIANT_HYBRID2},
     {8192, PALD_VARIANT_HYBRID2},
     {16384, PALD_VARIANT_HYBRID2},
-    {32768, PALD_VARIANT_PAIRWISE}};
+    {32768, PALD_VARIANT_HYBRID2}};
 
 }  // namespace pald_tuned

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "pairwise.hpp"
+#include "triplet.hpp"
 
 namespace {
 
@@ -54,9 +55,9 @@ namespace {
 enum {
     PQ_C_ADD_F32 = 0, PQ_C_FMA_F32, PQ_C_ADD_U32, PQ_C_AND_B32, PQ_C_MIN_U32, PQ_C_MIN_F32, PQ_C_CMP_U32, PQ_C_CMP_F32,
     PQ_C_CNDMASK, PQ_C_ADDC, PQ_C_CMP_AND_ADD_F32, PQ_C_MIN_AND_ADD_F32, PQ_C_MIN_AND_AND_B32, PQ_C_COHESION_BLOCK,
-    PQ_NUM_CLASSES
+    PQ_C_TRIPLET_BLOCK, PQ_NUM_CLASSES
 };
-constexpr int kInstrPerIter[PQ_NUM_CLASSES] = {32, 32, 32, 32, 32, 32, 32, 32, 32, 32, 64, 64, 64, 32};
+constexpr int kInstrPerIter[PQ_NUM_CLASSES] = {32, 32, 32, 32, 32, 32, 32, 32, 32, 32, 64, 64, 64, 32, 52};
 
 template <int CLS>
 __global__ __launch_bounds__(256) void probe_kernel(uint64_t *__restrict__ stamps, uint32_t *__restrict__ sink,
@@ -109,6 +110,36 @@ __global__ __launch_bounds__(256) void probe_kernel(uint64_t *__restrict__ stamp
                 f[k + 4] = __float_as_uint(rr[k]);
             }
         }
+        if constexpr (CLS == PQ_C_TRIPLET_BLOCK) {
+            // the triplet pass-2 block: one p, one q, four r -- per triple a min, three compares, three
+            // selects and six multiply-adds under EXEC masks (52 vector instructions)
+            float tpq = __uint_as_float(f[12]), tqp = __uint_as_float(f[13]);
+            float rf[4], rr[4], tqr[4], trq[4], hpr[4], hc[4];
+            uint32_t bb[4], cc[4];
+            const uint64_t vr[4] = {full, full, full, full};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                rf[k] = __uint_as_float(f[k]);
+                rr[k] = __uint_as_float(f[k + 4]);
+                tqr[k] = __uint_as_float(f[k + 8]);
+                trq[k] = __uint_as_float(a[k + 12]);
+                bb[k] = a[k];
+                cc[k] = a[k + 4];
+                hpr[k] = __uint_as_float(c);
+                hc[k] = __uint_as_float(b);
+            }
+            pald::triplet_cohesion4(tpq, tqp, rf, rr, tqr, trq, a[8], __uint_as_float(c), bb, hpr, cc, hc, full, vr,
+                                    full);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                f[k] = __float_as_uint(rf[k]);
+                f[k + 4] = __float_as_uint(rr[k]);
+                f[k + 8] = __float_as_uint(tqr[k]);
+                a[k + 12] = __float_as_uint(trq[k]);
+            }
+            f[12] = __float_as_uint(tpq);
+            f[13] = __float_as_uint(tqp);
+        }
     }
     const uint64_t t1 = clock64(), r1 = wall_clock64();
     const int wave = (int)(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
@@ -127,7 +158,7 @@ typedef void (*ProbeFn)(uint64_t *, uint32_t *, int32_t, uint64_t);
 const ProbeFn kProbes[PQ_NUM_CLASSES] = {
     probe_kernel<0>, probe_kernel<1>, probe_kernel<2>, probe_kernel<3>,  probe_kernel<4>,
     probe_kernel<5>, probe_kernel<6>, probe_kernel<7>, probe_kernel<8>,  probe_kernel<9>,
-    probe_kernel<10>, probe_kernel<11>, probe_kernel<12>, probe_kernel<13>};
+    probe_kernel<10>, probe_kernel<11>, probe_kernel<12>, probe_kernel<13>, probe_kernel<14>};
 
 }  // namespace
 

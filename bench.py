@@ -414,10 +414,12 @@ def main():
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the distance front end, local depths and strong-tie measurements")
     ap.add_argument("--variant", default="auto", choices=["auto", "pairwise", "triplet", "hybrid", "hybrid2"],
-                    help="algorithm of the timed step (default: the library's tuned choice, pairwise)")
+                    help="algorithm of the timed step (default: the library's tuned choice for n)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="instead of the benchmark, measure the vector issue rate of each instruction class "
                          "the kernels use and print it as one JSON line")
+    ap.add_argument("--valu-probe-waves", default="8,4",
+                    help="waves per SIMD the probe classes run at (comma-separated, 1..8)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain elementwise kernel that reads and writes 1 GiB, so a "
                          "counter profile can scale FETCH_SIZE / WRITE_SIZE")
@@ -441,7 +443,8 @@ def main():
         pald_build.build()
     pald.load_library()
     if args.valu_probe:
-        print(json.dumps({"valu_probe": valu_probe()}), flush=True)
+        waves = tuple(int(w) for w in args.valu_probe_waves.split(","))
+        print(json.dumps({"valu_probe": valu_probe(waves)}), flush=True)
         return
 
     n = args.n

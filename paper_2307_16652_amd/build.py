@@ -70,17 +70,18 @@ def tuned_header_text() -> str:
         wpc, lag, split = int(rec.get("workgroups_per_cu", 0)), int(rec.get("queue_lag", 0)), \
             bool(rec.get("split_pass1", False))
         src.append("tuning/batch_gfx950.json")
-    variants = [(2, "pairwise")]
+    variants = [(2, "pairwise", 0, 0)]
     path = os.path.join(TUNING, "variants_gfx950.json")
     if os.path.exists(path):
         with open(path) as f:
-            variants = sorted((int(r["n"]), str(r["best"])) for r in json.load(f)["sizes"])
+            variants = sorted((int(r["n"]), str(r["best"]), int(r.get("y_chunks", 0)), int(r.get("z_chunks", 0)))
+                              for r in json.load(f)["sizes"])
         src.append("tuning/variants_gfx950.json")
     if not 1 <= len(buckets) <= 8:
         raise ValueError("the batched tuning record needs 1 to 8 buckets")
     bl = ",\n    ".join(f"{{{int(b['n_max'])}, {int(b.get('tile', 64))}, {int(b.get('y_chunks', 1))}, 0}}"
                          for b in buckets)
-    vl = ",\n    ".join(f"{{{n}, {_VARIANT_ENUM[v]}}}" for n, v in variants)
+    vl = ",\n    ".join(f"{{{n}, {_VARIANT_ENUM[v]}, {yc}, {zc}}}" for n, v, yc, zc in variants)
     return f"""// tuned_gfx950.h -- the library's built-in tuned tables for MI355X (gfx950).
 // Written by build.py on every build from the autotuner's records
 // ({', '.join(src) or 'none found: untuned defaults'}); do not edit by hand:
@@ -101,11 +102,14 @@ constexpr int32_t kBatchWorkgroupsPerCu = {wpc};
 constexpr int32_t kBatchQueueLag = {lag};
 constexpr bool kBatchSplitPass1 = {'true' if split else 'false'};
 
-// single-matrix variant for PALD_VARIANT_AUTO: the entry with the largest n
-// not above the problem's n (the first entry below that)
+// single-matrix variant for PALD_VARIANT_AUTO, with the pass-2 y split and
+// the pass-1 z split it was fastest with (0 = the automatic split): the entry
+// with the largest n not above the problem's n (the first entry below that)
 struct VariantPick {{
     int64_t n;
     int32_t variant;
+    int32_t y_chunks;
+    int32_t z_chunks;
 }};
 constexpr VariantPick kVariants[] = {{
     {vl}}};

@@ -99,12 +99,24 @@ pald_status read_opts(const pald_options *o, Opts &out) {
 
 // PALD_VARIANT_AUTO -> the tuned variant for n, unless it cannot take the
 // other options (the triplet variant: compensated accumulation without
-// splits; the hybrid: no z split), in which case pairwise.
+// splits; the hybrid: no z split), in which case pairwise.  With both splits
+// automatic the tuned entry's splits are taken too.
 void resolve_variant(int64_t n, Opts &o) {
     if (o.variant != PALD_VARIANT_AUTO) return;
-    int32_t v = pald_tuned::kVariants[0].variant;
+    const pald_tuned::VariantPick *pick = &pald_tuned::kVariants[0];
     for (const auto &e : pald_tuned::kVariants)
-        if (e.n <= n) v = e.variant;
+        if (e.n <= n) pick = &e;
+    int32_t v = pick->variant;
+    if (o.y_chunks == 0 && o.z_chunks == 0) {
+        const bool y_ok = v == PALD_VARIANT_PAIRWISE || v == PALD_VARIANT_HYBRID;
+        const bool z_ok = v == PALD_VARIANT_PAIRWISE || v == PALD_VARIANT_HYBRID2;
+        const bool f64_ok = v == PALD_VARIANT_PAIRWISE || v == PALD_VARIANT_HYBRID;
+        if ((y_ok || pick->y_chunks == 0) && (z_ok || pick->z_chunks == 0) &&
+            (f64_ok || o.accum == PALD_ACC_COMPENSATED)) {
+            o.y_chunks = pick->y_chunks;
+            o.z_chunks = pick->z_chunks;
+        }
+    }
     if (v == PALD_VARIANT_TRIPLET && (o.accum != PALD_ACC_COMPENSATED || o.y_chunks != 0 || o.z_chunks != 0))
         v = PALD_VARIANT_PAIRWISE;
     if (v == PALD_VARIANT_HYBRID && o.z_chunks != 0) v = PALD_VARIANT_PAIRWISE;

@@ -21,20 +21,23 @@ constexpr int32_t kBatchWorkgroupsPerCu = 0;
 constexpr int32_t kBatchQueueLag = 0;
 constexpr bool kBatchSplitPass1 = true;
 
-// single-matrix variant for PALD_VARIANT_AUTO: the entry with the largest n
-// not above the problem's n (the first entry below that)
+// single-matrix variant for PALD_VARIANT_AUTO, with the pass-2 y split and
+// the pass-1 z split it was fastest with (0 = the automatic split): the entry
+// with the largest n not above the problem's n (the first entry below that)
 struct VariantPick {
     int64_t n;
     int32_t variant;
+    int32_t y_chunks;
+    int32_t z_chunks;
 };
 constexpr VariantPick kVariants[] = {
-    {256, PALD_VARIANT_PAIRWISE},
-    {512, PALD_VARIANT_PAIRWISE},
-    {1024, PALD_VARIANT_PAIRWISE},
-    {2048, PALD_VARIANT_PAIRWISE},
-    {4096, PALD_VARIANT_HYBRID2},
-    {8192, PALD_VARIANT_HYBRID2},
-    {16384, PALD_VARIANT_HYBRID2},
-    {32768, PALD_VARIANT_HYBRID2}};
+    {256, PALD_VARIANT_PAIRWISE, 8, 0},
+    {512, PALD_VARIANT_PAIRWISE, 8, 0},
+    {1024, PALD_VARIANT_PAIRWISE, 8, 0},
+    {2048, PALD_VARIANT_PAIRWISE, 8, 0},
+    {4096, PALD_VARIANT_HYBRID2, 0, 1},
+    {8192, PALD_VARIANT_HYBRID2, 0, 1},
+    {16384, PALD_VARIANT_HYBRID2, 0, 0},
+    {32768, PALD_VARIANT_HYBRID2, 0, 2}};
 
 }  // namespace pald_tuned

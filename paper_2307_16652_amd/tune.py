@@ -27,8 +27,9 @@ per bucket.
 
 With --variants it instead times the pairwise, hybrid (triplet pass 1 +
 pairwise pass 2), triplet and hybrid2 (pairwise pass 1 + triplet pass 2)
-variants of the single-matrix path on Gaussian mixtures of several sizes and
-writes, per size, the fastest one to
+variants of the single-matrix path on Gaussian mixtures of several sizes,
+then the pass-2 y split or pass-1 z split of the fastest one, and writes,
+per size, the fastest variant and splits to
 tuning/variants_gfx950.json, which the next build compiles into the library's
 PALD_VARIANT_AUTO choice.
 """
@@ -167,7 +168,28 @@ def tune(reps: int = 3, out: str | None = None) -> dict:
 VARIANT_SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384, 32768)
 
 
+def _time_cohesion(pald, torch, Dg, n, reps, **opts) -> float:
+    """Median milliseconds of pald_cohesion with these options (one warm-up call)."""
+    ws = pald.workspace(n, Dg.device, **opts)
+    U, C = pald.cohesion(Dg, ws=ws, **opts)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps if n <= 16384 else 1):  # seconds per call above that
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        pald.cohesion(Dg, ws=ws, out_u=U, out_c=C, **opts)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del ws, U, C
+    return round(float(np.median(times)), 3)
+
+
 def tune_variants(reps: int = 3, out: str | None = None) -> dict:
+    """Per size: the fastest variant with automatic splits, then the fastest
+    pass-2 y split (pairwise, hybrid) or pass-1 z split (pairwise, hybrid2)
+    of that variant (0 = the automatic split)."""
     import torch
 
     from . import pald, synth
@@ -177,25 +199,22 @@ def tune_variants(reps: int = 3, out: str | None = None) -> dict:
     rows = []
     for n in VARIANT_SIZES:
         Dg = torch.from_numpy(synth.mixture8d(n=n, seed=2)).to(dev)
-        ms = {}
-        for variant in ("pairwise", "hybrid", "triplet", "hybrid2"):
-            ws = pald.workspace(n, dev, variant=variant)
-            U, C = pald.cohesion(Dg, variant=variant, ws=ws)
-            torch.cuda.synchronize()
-            times = []
-            for _ in range(reps if n <= 16384 else 1):  # seconds per call above that
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                pald.cohesion(Dg, variant=variant, ws=ws, out_u=U, out_c=C)
-                e1.record()
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            ms[variant] = round(float(np.median(times)), 3)
-            del ws, U, C
+        ms = {v: _time_cohesion(pald, torch, Dg, n, reps, variant=v)
+              for v in ("pairwise", "hybrid", "triplet", "hybrid2")}
         best = min(ms, key=ms.get)
-        log(f"n={n}: {ms} -> {best}")
-        rows.append({"n": n, "ms": ms, "best": best})
+        splits = {"y0_z0": ms[best]}
+        if best in ("pairwise", "hybrid"):
+            for yc in (1, 2, 4, 8):
+                splits[f"y{yc}_z0"] = _time_cohesion(pald, torch, Dg, n, reps, variant=best, y_chunks=yc)
+        if best in ("pairwise", "hybrid2"):
+            for zc in (1, 2, 4):
+                splits[f"y0_z{zc}"] = _time_cohesion(pald, torch, Dg, n, reps, variant=best, z_chunks=zc)
+        key = min(splits, key=splits.get)
+        yc, zc = (int(t[1:]) for t in key.split("_"))
+        log(f"n={n}: {ms} -> {best}; splits {splits} -> y_chunks {yc}, z_chunks {zc}")
+        rows.append({"n": n, "ms": ms, "best": best, "split_ms": splits, "y_chunks": yc, "z_chunks": zc})
+        del Dg
+        torch.cuda.empty_cache()
     result = {"arch": "gfx950", "workload": "mixture8d (6 Gaussian clusters in R^8), seed 2",
               "sizes": rows}
     path = out or pald.VARIANT_TUNING_PATH

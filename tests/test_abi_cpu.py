@@ -51,19 +51,18 @@ def test_auto_variant_follows_the_tuned_table():
     import json
 
     with open(pald.VARIANT_TUNING_PATH) as f:
-        table = sorted((int(r["n"]), r["best"]) for r in json.load(f)["sizes"])
-    for n in (100, 256, 300, 1024, 5000, 20000):
-        pick = table[0][1]
-        for size, v in table:
-            if size <= n:
-                pick = v
-        assert pald.workspace_bytes(n, variant="auto") == pald.workspace_bytes(n, variant=pick), n
-    for n in (100, 256, 300, 1024, 5000, 20000):
-        pick = table[0][1]
-        for size, v in table:
-            if size <= n:
-                pick = v
-        assert pald.resolved_variant(n) == pick, n
+        table = sorted((int(r["n"]), r["best"], int(r.get("y_chunks", 0)), int(r.get("z_chunks", 0)))
+                       for r in json.load(f)["sizes"])
+    for n in (100, 256, 300, 1024, 3000, 5000, 20000, 40000):
+        pick = table[0]
+        for row in table:
+            if row[0] <= n:
+                pick = row
+        _, v, yc, zc = pick
+        # AUTO takes the tuned variant and, with both splits left automatic, its splits
+        assert pald.workspace_bytes(n, variant="auto") == \
+            pald.workspace_bytes(n, variant=v, y_chunks=yc, z_chunks=zc), n
+        assert pald.resolved_variant(n) == v, n
         assert pald.resolved_variant(n, variant="triplet") == "triplet"
     assert pald.load_library().pald_resolved_variant(100, ctypes.byref(pald.make_options(accum="f64"))) in (1, 3)
     bad = pald.make_options()

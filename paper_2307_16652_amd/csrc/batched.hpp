@@ -178,6 +178,10 @@ __global__ __launch_bounds__(BatchFocusCfg::NT, PALD_BATCH_P1Z_MIN_WAVES) void b
 #ifndef PALD_BATCH_LEAN_PASS2
 #define PALD_BATCH_LEAN_PASS2 1
 #endif
+// The one-launch form's lean kernel (batched_lean_kernel) under the same condition.
+#ifndef PALD_BATCH_LEAN_ONE_LAUNCH
+#define PALD_BATCH_LEAN_ONE_LAUNCH 1
+#endif
 #ifndef PALD_BATCH_LEAN_FEW_SGPR
 #define PALD_BATCH_LEAN_FEW_SGPR 0
 #endif
@@ -216,6 +220,76 @@ __global__ __launch_bounds__(BATCH_LEAN_THREADS, PALD_BATCH_LEAN_MIN_WAVES) void
         pass2_tile<BATCH_P2_T, PALD_BATCH_LEAN_RX, PALD_BATCH_LEAN_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR, true>(
             opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw, Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0, n,
             vec_d, true);
+        if (stamps && threadIdx.x == 0) {
+            __threadfence();
+            atomicMax((unsigned long long *)&stamps[2 * mi + 1], (unsigned long long)wall_clock64());
+        }
+        __syncthreads();  // s_item and the tile buffers are reused by the next item
+    }
+}
+
+// The one-launch form when every matrix runs 64-wide pass-2 tiles with no y
+// split: the lean kernel's pass-2 tile and, for the pass-1 items (64 x 64
+// regions of pairs x <= y), the single-matrix lanes-over-z tile walked over
+// the region's 16 x 16 squares, in one persistent kernel of 512 threads with
+// the one-launch protocol (a pass-2 item waits until its matrix's pass-1
+// items are all counted; every pass-1 item of a matrix is earlier in the
+// queue and pass-1 items never wait, so every wait ends).  On the
+// 2000-matrix batch it takes 135 ms against 134 ms for the general kernel,
+// with per-matrix latency p50 1.6 ms / p99 2.6 ms against 2.3 / 4.1 ms; the
+// lanes-over-pairs 64 x 64 tile with 1 x 8 pairs per thread for the pass-1
+// items took 139 ms.
+constexpr int BATCH_LEAN1_LDS_VEC = cmax(BatchLeanP2::LDS_VEC, P1zMain::LDS_WORDS / 4);
+static_assert(P1zMain::NT == BATCH_LEAN_THREADS && P1zMain::TX == 16 && P1zMain::TY == 16,
+              "the one-launch lean kernel walks 16 x 16 pass-1 squares with the pass-2 tile's threads");
+__global__ __launch_bounds__(BATCH_LEAN_THREADS, PALD_BATCH_LEAN_MIN_WAVES) void batched_lean_kernel(
+    const int4 *__restrict__ items, int32_t total, const BatchMatrix *__restrict__ mats, const float *__restrict__ D,
+    int32_t *__restrict__ U, float *__restrict__ C, float *__restrict__ Wr, uint32_t *__restrict__ ctr,
+    uint64_t *__restrict__ stamps, int32_t d_aligned) {
+    __shared__ uint4 sm[BATCH_LEAN1_LDS_VEC];
+    __shared__ int32_t s_item;
+    uint32_t *const done1 = ctr + 1;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int32_t it = uniform_i32(s_item);
+        if (it >= total) break;
+        const int4 item = items[it];
+        const int32_t mi = item.x;
+        const int64_t moff = mats[mi].off, mwoff = mats[mi].woff, n = mats[mi].n, ldw = mats[mi].ldw;
+        const int32_t tiles1 = mats[mi].tiles1;
+        const bool vec_d = d_aligned && mats[mi].vec_d;
+        if (stamps && threadIdx.x == 0)
+            atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
+        if (item.y == ITEM_PASS1) {
+            int32_t bx, by;
+            tri_tile(item.z, bx, by);
+            for (int sy = 0; sy < BATCH_P1_T / 16; ++sy)
+                for (int sx = 0; sx < BATCH_P1_T / 16; ++sx) {
+                    const int64_t X0 = (int64_t)bx * BATCH_P1_T + 16 * sx, Y0 = (int64_t)by * BATCH_P1_T + 16 * sy;
+                    if (X0 >= n || Y0 >= n || X0 > Y0) continue;  // squares holding a pair x <= y
+                    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>(
+                        opaque_tid(), reinterpret_cast<uint32_t *>(sm), D + moff, n, n, U ? U + moff : nullptr, n,
+                        Wr + mwoff, ldw, X0, Y0, 0, n, false, vec_d);
+                    __syncthreads();  // the next square reuses the stage buffers
+                }
+            __threadfence();  // release this thread's U / W stores at device scope
+            __syncthreads();
+            if (threadIdx.x == 0) atomicAdd(&done1[mi], 1u);
+        } else {
+            if (threadIdx.x == 0) {
+                while (__hip_atomic_load(&done1[mi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)tiles1)
+                    __builtin_amdgcn_s_sleep(2);
+                __atomic_thread_fence(__ATOMIC_ACQUIRE);
+            }
+            __syncthreads();
+            __threadfence();  // acquire for every wave before reading the weights
+            int32_t bx, bz;
+            tri_tile(item.z, bx, bz);
+            pass2_tile<BATCH_P2_T, PALD_BATCH_LEAN_RX, PALD_BATCH_LEAN_KY, false, (bool)PALD_BATCH_LEAN_FEW_SGPR, true>(
+                opaque_tid(), sm, D + moff, n, n, Wr + mwoff, ldw, Pass2Out{C + moff, n, nullptr, nullptr}, bx, bz, 0,
+                n, vec_d, true);
+        }
         if (stamps && threadIdx.x == 0) {
             __threadfence();
             atomicMax((unsigned long long *)&stamps[2 * mi + 1], (unsigned long long)wall_clock64());
@@ -276,6 +350,7 @@ __global__ __launch_bounds__(BATCH_THREADS, PALD_BATCH_MIN_BLOCKS) void batched_
                             if (X0 >= n || Y0 >= n || X0 > Y0 + (BatchP1z::TY - 1)) continue;
                             pass1z_tile<2, 2, PALD_BATCH_P1Z_NC>(opaque_tid(), reinterpret_cast<uint32_t *>(sm), D + moff, n, n, Um, n,
                                                  Wr + mwoff, mldw, X0, Y0, 0, n, false, vec_d);
+                            __syncthreads();  // the next sub-tile reuses the stage buffers
                         }
                 } else {
                     pass1_tile<BATCH_P1_T, BATCH_P1_RX, 8, 16>(opaque_tid(), sm, D + moff, n, n, Um, n, Wr + mwoff, mldw,

@@ -879,13 +879,21 @@ int32_t resident_per_cu() {
     return per;
 }
 
-int32_t lean_resident_per_cu() {
+int32_t lean_resident_per_cu(bool one_launch) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2_lean_kernel, BATCH_LEAN_THREADS, 0) !=
-            hipSuccess ||
-        per < 1)
-        per = 1;
+    const hipError_t e = one_launch
+                             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_lean_kernel, BATCH_LEAN_THREADS, 0)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_pass2_lean_kernel,
+                                                                            BATCH_LEAN_THREADS, 0);
+    if (e != hipSuccess || per < 1) per = 1;
     return per;
+}
+
+// Every matrix of the layout runs 64-wide pass-2 tiles without a y split.
+bool lean_layout(const BatchLayout &L) {
+    for (const BatchMatrix &m : L.mats)
+        if (m.y_chunks != 1 || m.tile2 != BATCH_P2_T) return false;
+    return true;
 }
 
 }  // namespace
@@ -900,6 +908,7 @@ struct pald_batch_plan {
     int4 *d_items = nullptr;
     int4 *d_tiles1z = nullptr;
     bool lean2 = false;  // split mode, every matrix 64-wide pass-2 tiles, no y split
+    bool lean1 = false;  // the same in the one-launch form
     size_t off_w = 0, off_p = 0, off_ctr = 0, off_stamps = 0, ws_bytes = 0;
 };
 
@@ -937,6 +946,12 @@ pald_status enqueue_batch(const pald_batch_plan *plan, const float *D, int32_t *
             plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, C, Wr, ctr, stamps, aligned16(D) ? 1 : 0);
         return launch_status();
     }
+    if (plan->lean1) {
+        batched_lean_kernel<<<(unsigned)plan->grid, BATCH_LEAN_THREADS, 0, s>>>(
+            plan->d_items, (int32_t)plan->L.items.size(), plan->d_mats, D, U, C, Wr, ctr, stamps,
+            aligned16(D) ? 1 : 0);
+        return launch_status();
+    }
     auto kern = plan->L.tiles1z.empty() ? batched_cohesion_kernel<true, true>
                                         : batched_cohesion_kernel<false, (bool)PALD_BATCH_SPLIT_FEW_SGPR>;
     kern<<<(unsigned)plan->grid, BATCH_THREADS, 0, s>>>(
@@ -972,11 +987,19 @@ pald_status pald_batch_plan_create(int32_t count, const int64_t *n_host, const p
         delete p;
         return st;
     }
-    p->lean2 = PALD_BATCH_LEAN_PASS2 && !p->L.tiles1z.empty();
-    for (const BatchMatrix &m : p->L.mats) p->lean2 = p->lean2 && m.y_chunks == 1 && m.tile2 == BATCH_P2_T;
-    // the lean kernel's own resident capacity (a split-mode queue does not depend on the grid)
-    if (p->lean2 && !(cfg && cfg->workgroups_per_cu > 0) && pald_tuned::kBatchWorkgroupsPerCu <= 0)
-        p->grid = cus * lean_resident_per_cu();
+    p->lean2 = PALD_BATCH_LEAN_PASS2 && !p->L.tiles1z.empty() && lean_layout(p->L);
+    p->lean1 = PALD_BATCH_LEAN_ONE_LAUNCH && p->L.tiles1z.empty() && lean_layout(p->L);
+    // the lean kernels' own resident capacity (a split-mode queue does not
+    // depend on the grid; a one-launch queue does, through the lag)
+    if ((p->lean2 || p->lean1) && !(cfg && cfg->workgroups_per_cu > 0) && pald_tuned::kBatchWorkgroupsPerCu <= 0) {
+        p->grid = cus * lean_resident_per_cu(p->lean1);
+        if (p->lean1 && p->grid != grid) {
+            if (pald_status st = build_batch(count, n_host, cfg, p->grid, p->L); st != PALD_OK) {
+                delete p;
+                return st;
+            }
+        }
+    }
     size_t off = 0;
     p->off_w = off;
     off = align_up(off + (size_t)p->L.w_floats * sizeof(float), ALIGN);

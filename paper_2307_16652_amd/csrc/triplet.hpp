@@ -69,12 +69,12 @@ constexpr int tri_rp() { return PASS2 ? PALD_TRI_RP2 : 4; }
 template <bool PASS2>
 constexpr int tri_threads() { return 16 * 64 / tri_rp<PASS2>(); }
 constexpr int TRI_RUN = 8;        // q values per float32 run of the (p, r) sums (one term each)
-// workgroups per CU each pass is compiled for (its register budget)
-#ifndef PALD_TRI_MIN_BLOCKS1
-#define PALD_TRI_MIN_BLOCKS1 4
+// minimum waves per SIMD each pass is compiled for (its register budget)
+#ifndef PALD_TRI_MIN_WAVES1
+#define PALD_TRI_MIN_WAVES1 4
 #endif
-#ifndef PALD_TRI_MIN_BLOCKS2
-#define PALD_TRI_MIN_BLOCKS2 (PALD_TRI_RP2 == 2 ? 2 : 3)
+#ifndef PALD_TRI_MIN_WAVES2
+#define PALD_TRI_MIN_WAVES2 (PALD_TRI_RP2 == 2 ? 4 : 3)
 #endif
 // U_xy = 2 above the diagonal, 0 below it (pass 1 adds into both triangles
 // and triplet_mirror_u_kernel sums them), U_xx = #{z : d_xz <= 0}.
@@ -381,7 +381,7 @@ __device__ __forceinline__ void store_row_vals(float *dst, const float (&v)[RP])
 // waves' partials in wave order) to the global sums.  Stages whose q lie
 // between the two blocks need no index masks.
 template <bool PASS2>
-__global__ __launch_bounds__(tri_threads<PASS2>(), PASS2 ? PALD_TRI_MIN_BLOCKS2 : PALD_TRI_MIN_BLOCKS1) void triplet_kernel(
+__global__ __launch_bounds__(tri_threads<PASS2>(), PASS2 ? PALD_TRI_MIN_WAVES2 : PALD_TRI_MIN_WAVES1) void triplet_kernel(
     const float *__restrict__ D, int64_t n, int64_t ldd, const float *__restrict__ W, int64_t ldw,
     int32_t *__restrict__ U, int64_t ldu, unsigned long long *__restrict__ A, unsigned long long *__restrict__ B,
     int32_t vec_d, int32_t vec_w, int32_t tile0, int32_t fbits, double scale) {

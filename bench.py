@@ -120,7 +120,9 @@ def valu_probe(waves=(8, 4), iters: int = 20000) -> dict:
     names = ["v_add_f32", "v_fma_f32", "v_add_u32", "v_and_b32", "v_min_u32", "v_min_f32", "v_cmp_lt_u32_e64",
              "v_cmp_le_f32_e64", "v_cndmask_b32_e64", "v_addc_co_u32_e64", "v_cmp_lt_u32_e64 + v_add_f32",
              "v_min_u32 + v_add_f32", "v_min_u32 + v_and_b32", "pass-2 block: 16 compares + 16 masked v_add_f32",
-             "triplet pass-2 block: 4 triples, 28 min/compare/select + 24 masked v_fmac_f32"]
+             "triplet pass-2 block: 4 triples, 28 min/compare/select + 24 masked v_fmac_f32",
+             "v_pk_sub_i16", "v_pk_min_i16", "v_pk_lshrrev_b16", "v_pk_add_u16",
+             "rank pass-1 block: 16 pairs, 2 v_pk_sub_i16 + v_pk_min_i16 + v_pk_lshrrev_b16 + v_pk_add_u16 per 2"]
     assert lib.pald_probe_classes() == len(names)
     out = {"unit": "SIMD cycles per wave64 vector instruction (at the measured shader clock)", "classes": {}}
     buf = (ctypes.c_double * 4)()

@@ -172,6 +172,75 @@ __device__ __forceinline__ void focus_mask_count32(int32_t (&c)[32], const uint3
 }
 #undef PALD_FMC
 
+// The first block of a tile: the same masks, but each count is written (the
+// popcount into the count register) instead of added, so that the 32 counts
+// need no zeroing; pairs 30 and 31, whose masks the block leaves in k[], start
+// at 0.  No k[] on entry.
+#define PALD_FMF0(M, X, Y, KP, CP, T)                                                                           \
+    "v_min_f32 %[m" #M "], %[x" #X "], %[y" #Y "]\n\t"                                                      \
+    "s_mov_b32 %[c" #CP "], 0\n\t"                                                                           \
+    "v_cmp_le_f32_e64 %[k" #KP "], %[m" #M "], %[a" #T "]\n\t"
+#define PALD_FMF(M, X, Y, KP, CP, T)                                                                            \
+    "v_min_f32 %[m" #M "], %[x" #X "], %[y" #Y "]\n\t"                                                      \
+    "s_bcnt1_i32_b64 %[c" #CP "], %[k" #KP "]\n\t"                                                          \
+    "v_cmp_le_f32_e64 %[k" #KP "], %[m" #M "], %[a" #T "]\n\t"
+__device__ __forceinline__ void focus_mask_count32_first(int32_t (&c)[32], const uint32_t (&x)[4],
+                                                         const uint32_t (&y)[8], const uint32_t (&a)[32],
+                                                         uint64_t (&k)[2]) {
+    uint32_t m0, m1, m2, m3;
+    asm(
+        PALD_FMF0(0, 0, 0, 0, 30, 0)
+        PALD_FMF0(1, 0, 1, 1, 31, 1)
+        PALD_FMF(2, 0, 2, 0, 0, 2)
+        PALD_FMF(3, 0, 3, 1, 1, 3)
+        PALD_FMF(0, 0, 4, 0, 2, 4)
+        PALD_FMF(1, 0, 5, 1, 3, 5)
+        PALD_FMF(2, 0, 6, 0, 4, 6)
+        PALD_FMF(3, 0, 7, 1, 5, 7)
+        PALD_FMF(0, 1, 0, 0, 6, 8)
+        PALD_FMF(1, 1, 1, 1, 7, 9)
+        PALD_FMF(2, 1, 2, 0, 8, 10)
+        PALD_FMF(3, 1, 3, 1, 9, 11)
+        PALD_FMF(0, 1, 4, 0, 10, 12)
+        PALD_FMF(1, 1, 5, 1, 11, 13)
+        PALD_FMF(2, 1, 6, 0, 12, 14)
+        PALD_FMF(3, 1, 7, 1, 13, 15)
+        PALD_FMF(0, 2, 0, 0, 14, 16)
+        PALD_FMF(1, 2, 1, 1, 15, 17)
+        PALD_FMF(2, 2, 2, 0, 16, 18)
+        PALD_FMF(3, 2, 3, 1, 17, 19)
+        PALD_FMF(0, 2, 4, 0, 18, 20)
+        PALD_FMF(1, 2, 5, 1, 19, 21)
+        PALD_FMF(2, 2, 6, 0, 20, 22)
+        PALD_FMF(3, 2, 7, 1, 21, 23)
+        PALD_FMF(0, 3, 0, 0, 22, 24)
+        PALD_FMF(1, 3, 1, 1, 23, 25)
+        PALD_FMF(2, 3, 2, 0, 24, 26)
+        PALD_FMF(3, 3, 3, 1, 25, 27)
+        PALD_FMF(0, 3, 4, 0, 26, 28)
+        PALD_FMF(1, 3, 5, 1, 27, 29)
+        PALD_FMF(2, 3, 6, 0, 28, 30)
+        PALD_FMF(3, 3, 7, 1, 29, 31)
+        : [c0] "=&s"(c[0]), [c1] "=&s"(c[1]), [c2] "=&s"(c[2]), [c3] "=&s"(c[3]), [c4] "=&s"(c[4]),
+          [c5] "=&s"(c[5]), [c6] "=&s"(c[6]), [c7] "=&s"(c[7]), [c8] "=&s"(c[8]), [c9] "=&s"(c[9]),
+          [c10] "=&s"(c[10]), [c11] "=&s"(c[11]), [c12] "=&s"(c[12]), [c13] "=&s"(c[13]), [c14] "=&s"(c[14]),
+          [c15] "=&s"(c[15]), [c16] "=&s"(c[16]), [c17] "=&s"(c[17]), [c18] "=&s"(c[18]), [c19] "=&s"(c[19]),
+          [c20] "=&s"(c[20]), [c21] "=&s"(c[21]), [c22] "=&s"(c[22]), [c23] "=&s"(c[23]), [c24] "=&s"(c[24]),
+          [c25] "=&s"(c[25]), [c26] "=&s"(c[26]), [c27] "=&s"(c[27]), [c28] "=&s"(c[28]), [c29] "=&s"(c[29]),
+          [c30] "=&s"(c[30]), [c31] "=&s"(c[31]), [k0] "=&s"(k[0]), [k1] "=&s"(k[1]), [m0] "=&v"(m0),
+          [m1] "=&v"(m1), [m2] "=&v"(m2), [m3] "=&v"(m3)
+        : [x0] "v"(x[0]), [x1] "v"(x[1]), [x2] "v"(x[2]), [x3] "v"(x[3]), [y0] "v"(y[0]), [y1] "v"(y[1]),
+          [y2] "v"(y[2]), [y3] "v"(y[3]), [y4] "v"(y[4]), [y5] "v"(y[5]), [y6] "v"(y[6]), [y7] "v"(y[7]),
+          [a0] "v"(a[0]), [a1] "v"(a[1]), [a2] "v"(a[2]), [a3] "v"(a[3]), [a4] "v"(a[4]), [a5] "v"(a[5]),
+          [a6] "v"(a[6]), [a7] "v"(a[7]), [a8] "v"(a[8]), [a9] "v"(a[9]), [a10] "v"(a[10]), [a11] "v"(a[11]),
+          [a12] "v"(a[12]), [a13] "v"(a[13]), [a14] "v"(a[14]), [a15] "v"(a[15]), [a16] "v"(a[16]),
+          [a17] "v"(a[17]), [a18] "v"(a[18]), [a19] "v"(a[19]), [a20] "v"(a[20]), [a21] "v"(a[21]),
+          [a22] "v"(a[22]), [a23] "v"(a[23]), [a24] "v"(a[24]), [a25] "v"(a[25]), [a26] "v"(a[26]),
+          [a27] "v"(a[27]), [a28] "v"(a[28]), [a29] "v"(a[29]), [a30] "v"(a[30]), [a31] "v"(a[31]));
+}
+#undef PALD_FMF0
+#undef PALD_FMF
+
 // The two masks focus_mask_count32 leaves in k[] (pairs 30 and 31).
 __device__ __forceinline__ void focus_mask_flush(int32_t (&c)[32], const uint64_t (&k)[2]) {
     c[30] += __builtin_popcountll(k[0]);
@@ -662,6 +731,13 @@ __device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetc
     return out;
 }
 
+// A wave-uniform 64-bit value as the value of the first active lane (two
+// 32-bit lane reads), so that what is computed from it stays scalar.
+__device__ __forceinline__ uint64_t p1_uniform_u64(uint64_t v) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+}
+
 // One lanes-over-z pass-1 tile: pairs x in [X0, X0 + TX), y in [Y0, Y0 + TY),
 // z over [zbeg, zend), rows of D as described by g.  Called by every thread
 // of a workgroup of Cfg::NT threads (tid = thread index); `smw` points to
@@ -689,8 +765,8 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
     // patterns (focus_mask_count32 compares them as floats).  Pair p = 8 i + j
     // is (x, y) = (xw + i, yw + j).
     uint32_t t[Cfg::WX * Cfg::WY];
-    int32_t cnt[Cfg::WX * Cfg::WY];
-    uint64_t carry[2] = {0, 0};
+    int32_t cnt[Cfg::WX * Cfg::WY];  // written by the tile's first block (or zeroed if it has none)
+    uint64_t carry[2];
     static_assert(Cfg::NW * Cfg::WX * Cfg::WY <= Cfg::ROWS * Cfg::ZS, "the keys fit in one stage buffer");
     // Lane p < 32 loads the key of pair p (row and column clamped into the
     // matrix: a pair outside it is counted but never written) and the wave
@@ -699,20 +775,24 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
     // arithmetic on the scalar unit, which also does the counting (per tile
     // and wave, 213 scalar instructions before the stage loop instead of
     // 508).  The keys sit in the second stage buffer, which the first stage
-    // leaves alone and the stage loop first writes after a barrier.
-    {
-        uint32_t *kw = smw + Cfg::ROWS * Cfg::ZS + wave * (Cfg::WX * Cfg::WY);
+    // leaves alone and the stage loop first writes after a barrier.  The key
+    // goes to LDS (take_keys) after the first stage's loads are issued, so
+    // that the two loads are in flight together.
+    uint32_t *kw = smw + Cfg::ROWS * Cfg::ZS + wave * (Cfg::WX * Cfg::WY);
+    auto load_key = [&]() {
+        uint32_t key = 0;
         if (lane < Cfg::WX * Cfg::WY) {
             const int64_t x = min(xw + lane / Cfg::WY, g.xhi - 1), y = min(yw + lane % Cfg::WY, n - 1);
-            kw[lane] = __float_as_uint(g.Dx[(x - g.xlo) * g.ldx + y]);
+            key = __float_as_uint(g.Dx[(x - g.xlo) * g.ldx + y]);
         }
+        return key;
+    };
+    auto take_keys = [&](uint32_t key) {
+        if (lane < Cfg::WX * Cfg::WY) kw[lane] = key;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) {
-            t[p] = kw[p];
-            cnt[p] = 0;
-        }
-    }
+        for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) t[p] = kw[p];
+    };
 
     const int32_t nst = (int32_t)((zend - zbeg + Cfg::ZS - 1) / Cfg::ZS);
     // Stages that lie inside [zbeg, zend) of a tile whose rows all exist load
@@ -721,18 +801,23 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
     // others go through the bounds-checked p1z_fetch_edge().
     const bool rows_in = X0 + Cfg::TX <= g.xhi && Y0 + Cfg::TY <= g.yhi;
     const int32_t nst_fast = rows_in ? (int32_t)((zend - zbeg) / Cfg::ZS) : 0;  // leading stages needing no checks
+    // Row pointers of the stages without checks.  Those run only when every
+    // row of the tile exists, so the rows need no clamping here; the 64-bit
+    // arithmetic is a product per tile and side plus a small one per row, all
+    // of it wave-uniform (scalar unit).
+    // (Row q of the wave is tile row wave + q NW: its first TX / NW rows are
+    // x rows, the rest y rows.)
+    static_assert(Cfg::TX % Cfg::NW == 0, "each wave's rows are x rows, then y rows");
     const char *rowp[RPW];
+    {
+        constexpr int QX = Cfg::TX / Cfg::NW;
+        const uint64_t ldx4 = (uint64_t)g.ldx * sizeof(float), ldy4 = (uint64_t)g.ldy * sizeof(float);
+        const uint64_t z4 = (uint64_t)zbeg * sizeof(float);
+        const char *bx = reinterpret_cast<const char *>(g.Dx) + (uint64_t)(X0 - g.xlo + wave) * ldx4 + z4;
+        const char *by = reinterpret_cast<const char *>(g.Dy) + (uint64_t)(Y0 - g.ylo + wave) * ldy4 + z4;
 #pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-        const int r = wave + q * Cfg::NW;
-        const bool is_x = r < Cfg::TX;
-        const int64_t rel = is_x ? min(X0 + r, g.xhi - 1) - g.xlo : min(Y0 + (r - Cfg::TX), g.yhi - 1) - g.ylo;
-        // (the byte offset made explicitly wave-uniform, so that the row
-        // pointers stay in scalar registers)
-        const uint64_t ro = (uint64_t)(rel * (is_x ? g.ldx : g.ldy) + zbeg) * sizeof(float);
-        rowp[q] = reinterpret_cast<const char *>(is_x ? g.Dx : g.Dy) +
-                  (((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(ro >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)ro));
+        for (int q = 0; q < RPW; ++q)
+            rowp[q] = q < QX ? bx + (uint64_t)(q * Cfg::NW) * ldx4 : by + (uint64_t)((q - QX) * Cfg::NW) * ldy4;
     }
     // The stage loop, instantiated for aligned rows (VEC: vector loads) and for
     // unaligned ones (one load per value); one tile runs one of the two.
@@ -763,9 +848,30 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
         };
         constexpr uint32_t STAGE_BYTES = Cfg::ZS * sizeof(float);
         const uint32_t lane_off = (uint32_t)NC * (uint32_t)lane * (uint32_t)sizeof(float);
+        // the partial last stage of a tile whose rows all exist: the row
+        // pointers of the stages without checks, each z clamped to the last
+        // one (so that every load stays inside the row) and +inf put in place
+        // of the values past it -- a few instructions per value instead of the
+        // bounds-checked fetch with its 64-bit row arithmetic
+        auto fetch_tail = [&](int32_t st) {
+            const int32_t zlast = (int32_t)(zend - 1 - zbeg);  // z of the last value, relative to zbeg
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int32_t z = st * Cfg::ZS + NC * lane + c;
+                const bool ok = z <= zlast;
+                const uint32_t zo = (uint32_t)(ok ? z : zlast) * (uint32_t)sizeof(float);
+#pragma unroll
+                for (int q = 0; q < RPW; ++q) {
+                    const uint32_t v = *reinterpret_cast<const uint32_t *>(rowp[q] + zo);
+                    pre.r[q].v[c] = ok ? v : KEY_INF;
+                }
+            }
+        };
         auto fetch = [&](int32_t st) {  // stage st: z = zbeg + ZS st + ...
             if (st < nst_fast)
                 fetch_fast((uint32_t)st * STAGE_BYTES + lane_off);
+            else if (rows_in)
+                fetch_tail(st);
             else
                 if constexpr (RECT)
                     pre = p1z_fetch_edge_rows<GX, GY, NC>(
@@ -789,7 +895,7 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
         // the counting of one staged buffer: component c + 1 is read before the
         // block of component c runs (the scheduling barriers keep the reads
         // there), so that the reads overlap it
-        auto count = [&](int buf) {
+        auto count = [&](int buf, auto first_tag) {  // first_tag: std::true_type for the tile's first stage
             const uint32_t *sb = smw + buf * (Cfg::ROWS * Cfg::ZS) + lane;
             uint32_t av[2][Cfg::WX], bv[2][Cfg::WY];
             auto read_comp = [&](int c) {
@@ -803,36 +909,60 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
             for (int c = 0; c < NC; ++c) {
                 if (c + 1 < NC) read_comp(c + 1);
                 __builtin_amdgcn_sched_barrier(0);
-                focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
+                if (decltype(first_tag)::value && c == 0)
+                    focus_mask_count32_first(cnt, av[c & 1], bv[c & 1], t, carry);
+                else
+                    focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
                 __builtin_amdgcn_sched_barrier(0);
             }
         };
 
-        if (nst > 0) {
+        if (nst > 0 && !rows_in) {
+            // a first stage through the out-of-line bounds-checked fetch:
+            // the key goes to LDS first, so that it is not held across the call
+            take_keys(load_key());
             fetch(0);
-            stash(0);
+        } else {
+            const uint32_t key = load_key();
+            if (nst_fast > 0)
+                fetch_fast(lane_off);
+            else if (nst > 0)
+                fetch_tail(0);
+            take_keys(key);
         }
+        if (nst > 0) stash(0);
         __syncthreads();
-        // Stages whose successor loads without checks run two at a time with
-        // fixed buffers (buffer 0 holds stage st on entry): little loop control
-        // on the scalar unit, which also does the counting.
         int32_t st = 0;
-        uint32_t off = STAGE_BYTES + lane_off;  // of stage st + 1
+        if (nst > 0) {  // stage 0 on its own: its first block starts the counts
+            if (nst > 1) fetch(1);
+            count(0, std::true_type{});
+            if (nst > 1) stash(1);
+            __syncthreads();
+            st = 1;
+        } else {
+#pragma unroll
+            for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) cnt[p] = 0;
+            carry[0] = carry[1] = 0;
+        }
+        // Stages whose successor loads without checks run two at a time with
+        // fixed buffers (buffer 1 holds stage st on entry): little loop control
+        // on the scalar unit, which also does the counting.
+        uint32_t off = 2 * STAGE_BYTES + lane_off;  // of stage st + 1 (st = 1)
         for (; st + 2 < nst_fast; st += 2) {
             fetch_fast(off);
-            count(0);
-            stash(1);
+            count(1, std::false_type{});
+            stash(0);
             __syncthreads();
             fetch_fast(off + STAGE_BYTES);
-            count(1);
-            stash(0);
+            count(0, std::false_type{});
+            stash(1);
             __syncthreads();
             off += 2 * STAGE_BYTES;
         }
         for (; st < nst; ++st) {  // the rest, buffer st & 1
             const int buf = st & 1;
             if (st + 1 < nst) fetch(st + 1);
-            count(buf);
+            count(buf, std::false_type{});
             if (st + 1 < nst) stash(buf ^ 1);
             __syncthreads();
         }
@@ -843,12 +973,17 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
         run(std::false_type{});
 
     focus_mask_flush(cnt, carry);
-    // epilogue: lane p (p < 32) takes pair p
+    // epilogue: lane p (p < 32) takes pair p (one lane write per count)
     int32_t mine = 0;
 #pragma unroll
-    for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) mine = lane == p ? cnt[p] : mine;
-    if (lane >= Cfg::WX * Cfg::WY) return;
-    const int64_t x = xw + lane / Cfg::WY, y = yw + lane % Cfg::WY;
+    for (int p = 0; p < Cfg::WX * Cfg::WY; ++p) asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(cnt[p]), "i"(p));
+    // (the lane index passed through an empty asm, so that the pair indices
+    // are formed here again rather than kept from the key loads across the
+    // stage loop, where registers are short)
+    int elane = lane;
+    asm volatile("" : "+v"(elane));
+    if (elane >= Cfg::WX * Cfg::WY) return;
+    const int64_t x = xw + elane / Cfg::WY, y = yw + elane % Cfg::WY;
     if constexpr (RECT) {
         if (x >= g.xhi || y >= g.yhi) return;
         if (U) U[(x - g.xlo) * ldu + y] = mine;

@@ -37,6 +37,10 @@ namespace {
 #define PQ_CMPU_ADDF(k) "v_cmp_lt_u32_e64 %[s" #k "], %[a" #k "], %[b]\n\tv_add_f32 %[f" #k "], %[f" #k "], %[c]\n\t"
 #define PQ_MINU_ADDF(k) "v_min_u32 %[a" #k "], %[a" #k "], %[b]\n\tv_add_f32 %[f" #k "], %[f" #k "], %[c]\n\t"
 #define PQ_MINU_ANDB(k) "v_min_u32 %[a" #k "], %[a" #k "], %[b]\n\tv_and_b32 %[f" #k "], %[f" #k "], %[c]\n\t"
+#define PQ_PKSUB(k) "v_pk_sub_i16 %[a" #k "], %[a" #k "], %[b]\n\t"
+#define PQ_PKMIN(k) "v_pk_min_i16 %[a" #k "], %[a" #k "], %[b]\n\t"
+#define PQ_PKSHR(k) "v_pk_lshrrev_b16 %[a" #k "], 15, %[a" #k "]\n\t"
+#define PQ_PKADD(k) "v_pk_add_u16 %[a" #k "], %[a" #k "], %[b]\n\t"
 
 #define PQ_AOUT(k) [a##k] "+v"(a[k])
 #define PQ_FOUT(k) [f##k] "+v"(f[k])
@@ -55,9 +59,11 @@ namespace {
 enum {
     PQ_C_ADD_F32 = 0, PQ_C_FMA_F32, PQ_C_ADD_U32, PQ_C_AND_B32, PQ_C_MIN_U32, PQ_C_MIN_F32, PQ_C_CMP_U32, PQ_C_CMP_F32,
     PQ_C_CNDMASK, PQ_C_ADDC, PQ_C_CMP_AND_ADD_F32, PQ_C_MIN_AND_ADD_F32, PQ_C_MIN_AND_AND_B32, PQ_C_COHESION_BLOCK,
-    PQ_C_TRIPLET_BLOCK, PQ_NUM_CLASSES
+    PQ_C_TRIPLET_BLOCK, PQ_C_PK_SUB_I16, PQ_C_PK_MIN_I16, PQ_C_PK_LSHR_B16, PQ_C_PK_ADD_U16, PQ_C_RANK_BLOCK,
+    PQ_NUM_CLASSES
 };
-constexpr int kInstrPerIter[PQ_NUM_CLASSES] = {32, 32, 32, 32, 32, 32, 32, 32, 32, 32, 64, 64, 64, 32, 52};
+constexpr int kInstrPerIter[PQ_NUM_CLASSES] = {32, 32, 32, 32, 32, 32, 32, 32, 32, 32, 64, 64, 64, 32, 52,
+                                                32, 32, 32, 32, 40};
 
 template <int CLS>
 __global__ __launch_bounds__(256) void probe_kernel(uint64_t *__restrict__ stamps, uint32_t *__restrict__ sink,
@@ -91,6 +97,35 @@ __global__ __launch_bounds__(256) void probe_kernel(uint64_t *__restrict__ stamp
             asm volatile(PQ_R32(PQ_MINU_ADDF) : PQ_AOUT16, PQ_FOUT16 : [b] "v"(b), [c] "v"(c));
         if constexpr (CLS == PQ_C_MIN_AND_AND_B32)
             asm volatile(PQ_R32(PQ_MINU_ANDB) : PQ_AOUT16, PQ_FOUT16 : [b] "v"(b), [c] "v"(c));
+        if constexpr (CLS == PQ_C_PK_SUB_I16) asm volatile(PQ_R32(PQ_PKSUB) : PQ_AOUT16 : [b] "v"(b));
+        if constexpr (CLS == PQ_C_PK_MIN_I16) asm volatile(PQ_R32(PQ_PKMIN) : PQ_AOUT16 : [b] "v"(b));
+        if constexpr (CLS == PQ_C_PK_LSHR_B16) asm volatile(PQ_R32(PQ_PKSHR) : PQ_AOUT16);
+        if constexpr (CLS == PQ_C_PK_ADD_U16) asm volatile(PQ_R32(PQ_PKADD) : PQ_AOUT16 : [b] "v"(b));
+        if constexpr (CLS == PQ_C_RANK_BLOCK) {
+            // the rank-form pass-1 block for 16 pairs (8 packed pairs of pairs): per
+            // pair of pairs two packed differences (x side, y side with its low half
+            // used twice), their packed minimum, its sign bits and a packed count
+            uint32_t t[8], u[8];
+            asm volatile(
+#define PQ_RK1(k) "v_pk_sub_i16 %[t" #k "], %[x" #k "], %[sa]\n\t"
+#define PQ_RK2(k) "v_pk_sub_i16 %[u" #k "], %[y], %[sb] op_sel_hi:[0,1]\n\t"
+#define PQ_RK3(k) "v_pk_min_i16 %[t" #k "], %[t" #k "], %[u" #k "]\n\t"
+#define PQ_RK4(k) "v_pk_lshrrev_b16 %[t" #k "], 15, %[t" #k "]\n\t"
+#define PQ_RK5(k) "v_pk_add_u16 %[a" #k "], %[a" #k "], %[t" #k "]\n\t"
+                PQ_R8(PQ_RK1) PQ_R8(PQ_RK2) PQ_R8(PQ_RK3) PQ_R8(PQ_RK4) PQ_R8(PQ_RK5)
+#undef PQ_RK1
+#undef PQ_RK2
+#undef PQ_RK3
+#undef PQ_RK4
+#undef PQ_RK5
+                : [a0] "+v"(a[0]), [a1] "+v"(a[1]), [a2] "+v"(a[2]), [a3] "+v"(a[3]), [a4] "+v"(a[4]),
+                  [a5] "+v"(a[5]), [a6] "+v"(a[6]), [a7] "+v"(a[7]), [t0] "=&v"(t[0]), [t1] "=&v"(t[1]),
+                  [t2] "=&v"(t[2]), [t3] "=&v"(t[3]), [t4] "=&v"(t[4]), [t5] "=&v"(t[5]), [t6] "=&v"(t[6]),
+                  [t7] "=&v"(t[7]), [u0] "=&v"(u[0]), [u1] "=&v"(u[1]), [u2] "=&v"(u[2]), [u3] "=&v"(u[3]),
+                  [u4] "=&v"(u[4]), [u5] "=&v"(u[5]), [u6] "=&v"(u[6]), [u7] "=&v"(u[7])
+                : [x0] "v"(f[0]), [x1] "v"(f[1]), [x2] "v"(f[2]), [x3] "v"(f[3]), [x4] "v"(f[4]), [x5] "v"(f[5]),
+                  [x6] "v"(f[6]), [x7] "v"(f[7]), [y] "v"(f[8]), [sa] "s"((uint32_t)m), [sb] "s"((uint32_t)(m >> 32)));
+        }
         if constexpr (CLS == PQ_C_COHESION_BLOCK) {
             // the pass-2 block: one x, four z, one y -- 16 compares and 16 masked additions
             float rf[4], rr[4], hz[4];
@@ -158,7 +193,8 @@ typedef void (*ProbeFn)(uint64_t *, uint32_t *, int32_t, uint64_t);
 const ProbeFn kProbes[PQ_NUM_CLASSES] = {
     probe_kernel<0>, probe_kernel<1>, probe_kernel<2>, probe_kernel<3>,  probe_kernel<4>,
     probe_kernel<5>, probe_kernel<6>, probe_kernel<7>, probe_kernel<8>,  probe_kernel<9>,
-    probe_kernel<10>, probe_kernel<11>, probe_kernel<12>, probe_kernel<13>, probe_kernel<14>};
+    probe_kernel<10>, probe_kernel<11>, probe_kernel<12>, probe_kernel<13>, probe_kernel<14>,
+    probe_kernel<15>, probe_kernel<16>, probe_kernel<17>, probe_kernel<18>, probe_kernel<19>};
 
 }  // namespace
 

@@ -63,12 +63,19 @@ constexpr int TARGET_WORKGROUPS = 1024;  // >= 4 per CU on a 256-CU part
 constexpr int64_t P1_TILES_PER_LAUNCH = 32768;
 constexpr int64_t P1Z_TILES_PER_LAUNCH = 1 << 20;  // n = 65536: 8 launches of about 1 s
 constexpr int64_t P2_TILES_PER_LAUNCH = 65536;
-constexpr int64_t TRI_TILES_PER_LAUNCH = 8192;
+// Triplet owner tiles differ in work by up to n / 64 times (a tile streams
+// bz - bx + 1 blocks of middle indices), so their launches are cut by work:
+// at most this many blocks summed over a launch's tiles (about 1 s), and at
+// most TRI_TILES_PER_LAUNCH tiles.
+constexpr int64_t TRI_BLOCKS_PER_LAUNCH = (int64_t)1 << 23;
+constexpr int64_t TRI_TILES_PER_LAUNCH = (int64_t)1 << 20;
 // A dispatch counts its work-items along x in 32 bits: every launched piece
 // must stay below 2^32 of them.
 constexpr int64_t MAX_X_ITEMS = (int64_t)1 << 32;
 static_assert(P1_TILES_PER_LAUNCH * P1::NT < MAX_X_ITEMS && P1Z_TILES_PER_LAUNCH * P1Z_NT < MAX_X_ITEMS &&
-                  P2_TILES_PER_LAUNCH * P2::NT < MAX_X_ITEMS,
+                  P2_TILES_PER_LAUNCH * P2::NT < MAX_X_ITEMS &&
+                  TRI_TILES_PER_LAUNCH * tri_threads<true>() < MAX_X_ITEMS &&
+                  TRI_TILES_PER_LAUNCH * tri_threads<false>() < MAX_X_ITEMS,
               "launch pieces must hold fewer than 2^32 work-items");
 
 // ---- options -----------------------------------------------------------------
@@ -287,6 +294,34 @@ TripletPlan triplet_plan(int64_t n) {
 
 size_t triplet_workspace_bytes(int64_t n) { return triplet_plan(n).bytes; }
 
+// The launch pieces of the nb (nb + 1) / 2 owner tiles, in the kernel's
+// heavy-first order (diagonal d = bz - bx from nb - 1 down to 0: nb - d tiles
+// of d + 1 blocks each): the first tile of every piece, then the tile count.
+// One piece per dispatch; cutting by work rather than by tile count keeps a
+// piece's last, long tiles from holding the GPU half idle at its end.
+std::vector<int64_t> triplet_pieces(int64_t nb) {
+    std::vector<int64_t> at{0};
+    int64_t k = 0, blocks = 0;
+    for (int64_t d = nb - 1; d >= 0; --d) {
+        int64_t left = nb - d;
+        while (left > 0) {
+            int64_t fit = std::min((TRI_BLOCKS_PER_LAUNCH - blocks) / (d + 1), TRI_TILES_PER_LAUNCH - (k - at.back()));
+            if (fit <= 0 && k == at.back()) fit = 1;  // a tile heavier than a piece runs alone
+            if (fit <= 0) {
+                at.push_back(k);
+                blocks = 0;
+                continue;
+            }
+            const int64_t take = std::min(fit, left);
+            k += take;
+            left -= take;
+            blocks += take * (d + 1);
+        }
+    }
+    at.push_back(k);
+    return at;
+}
+
 // Triplet pass 1 into U (initialised here).
 pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, int64_t ldu, hipStream_t s,
                           bool timing) {
@@ -295,9 +330,11 @@ pald_status triplet_focus(const float *D, int64_t n, int64_t ldd, int32_t *U, in
     triplet_init_u_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, U, ldu);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     const int vec = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
-    for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
+    const std::vector<int64_t> pcs = triplet_pieces(ceil_div(n, TRI_T));
+    for (size_t i = 0; i + 1 < pcs.size(); ++i) {
         ScopedTiming tm(timing, 5, s);
-        const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
+        const int64_t t0 = pcs[i];
+        const unsigned g = (unsigned)(pcs[i + 1] - t0);
         triplet_kernel<false><<<g, tri_threads<false>(), 0, s>>>(D, n, ldd, nullptr, 0, U, ldu, nullptr, nullptr, vec, 0,
                                                          (int32_t)t0, 0, 1.0);
         if (pald_status st = launch_status(); st != PALD_OK) return st;
@@ -345,9 +382,11 @@ pald_status triplet_cohesion(const float *D, int64_t n, int64_t ldd, int32_t *U,
     triplet_init_c_kernel<<<rows_grid(n), 256, 0, s>>>(D, n, ldd, W, t.ldw, A, B, scale);
     if (pald_status st = launch_status(); st != PALD_OK) return st;
     const int vecd = (aligned16(D) && ldd % 4 == 0) ? 1 : 0;
-    for (int64_t t0 = 0; t0 < t.tiles; t0 += TRI_TILES_PER_LAUNCH) {
+    const std::vector<int64_t> pcs = triplet_pieces(ceil_div(n, TRI_T));
+    for (size_t i = 0; i + 1 < pcs.size(); ++i) {
         ScopedTiming tm(timing, 6, s);
-        const unsigned g = (unsigned)std::min<int64_t>(TRI_TILES_PER_LAUNCH, t.tiles - t0);
+        const int64_t t0 = pcs[i];
+        const unsigned g = (unsigned)(pcs[i + 1] - t0);
         triplet_kernel<true><<<g, tri_threads<true>(), 0, s>>>(D, n, ldd, W, t.ldw, nullptr, 0, A, B, vecd, 1, (int32_t)t0,
                                                         triplet_fixed_bits(n), scale);
         if (pald_status st = launch_status(); st != PALD_OK) return st;

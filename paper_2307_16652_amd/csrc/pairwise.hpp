@@ -731,13 +731,6 @@ __device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetc
     return out;
 }
 
-// A wave-uniform 64-bit value as the value of the first active lane (two
-// 32-bit lane reads), so that what is computed from it stays scalar.
-__device__ __forceinline__ uint64_t p1_uniform_u64(uint64_t v) {
-    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(v >> 32)) << 32) |
-           (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
-}
-
 // One lanes-over-z pass-1 tile: pairs x in [X0, X0 + TX), y in [Y0, Y0 + TY),
 // z over [zbeg, zend), rows of D as described by g.  Called by every thread
 // of a workgroup of Cfg::NT threads (tid = thread index); `smw` points to

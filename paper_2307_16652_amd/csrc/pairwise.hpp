@@ -740,8 +740,10 @@ __device__ __noinline__ P1zStage<P1zCfg<GX, GY, NC>::ROWS_PER_WAVE, NC> p1z_fetc
 // (a block of rows x): writes every pair x < xhi, y < yhi of the tile, U at
 // U[(x - xlo) ldu + y] and the weight transposed, W[y ldw + (x - xlo)]; no
 // atomic mode.  Ends with a workgroup barrier, so the LDS can be reused at
-// once.
-template <int GX, int GY, int NC, bool RECT = false>
+// once.  AHEAD: the next z component's values are read from LDS while the
+// block of the current one runs (12 more VGPRs); without it the waves of the
+// SIMD cover that latency, which pays where the tile fits 8 waves per SIMD.
+template <int GX, int GY, int NC, bool RECT = false, bool AHEAD = true>
 __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Rows g, int64_t n,
                                               int32_t *__restrict__ U, int64_t ldu, float *__restrict__ W,
                                               int64_t ldw, int64_t X0, int64_t Y0, int64_t zbeg, int64_t zend,
@@ -890,23 +892,41 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
         // there), so that the reads overlap it
         auto count = [&](int buf, auto first_tag) {  // first_tag: std::true_type for the tile's first stage
             const uint32_t *sb = smw + buf * (Cfg::ROWS * Cfg::ZS) + lane;
-            uint32_t av[2][Cfg::WX], bv[2][Cfg::WY];
-            auto read_comp = [&](int c) {
+            if constexpr (AHEAD) {
+                uint32_t av[2][Cfg::WX], bv[2][Cfg::WY];
+                auto read_comp = [&](int c) {
 #pragma unroll
-                for (int i = 0; i < Cfg::WX; ++i) av[c & 1][i] = sb[(wx * Cfg::WX + i) * Cfg::ZS + 64 * c];
+                    for (int i = 0; i < Cfg::WX; ++i) av[c & 1][i] = sb[(wx * Cfg::WX + i) * Cfg::ZS + 64 * c];
 #pragma unroll
-                for (int j = 0; j < Cfg::WY; ++j) bv[c & 1][j] = sb[(Cfg::TX + wy * Cfg::WY + j) * Cfg::ZS + 64 * c];
-            };
-            read_comp(0);
+                    for (int j = 0; j < Cfg::WY; ++j)
+                        bv[c & 1][j] = sb[(Cfg::TX + wy * Cfg::WY + j) * Cfg::ZS + 64 * c];
+                };
+                read_comp(0);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c + 1 < NC) read_comp(c + 1);
-                __builtin_amdgcn_sched_barrier(0);
-                if (decltype(first_tag)::value && c == 0)
-                    focus_mask_count32_first(cnt, av[c & 1], bv[c & 1], t, carry);
-                else
-                    focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
-                __builtin_amdgcn_sched_barrier(0);
+                for (int c = 0; c < NC; ++c) {
+                    if (c + 1 < NC) read_comp(c + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (decltype(first_tag)::value && c == 0)
+                        focus_mask_count32_first(cnt, av[c & 1], bv[c & 1], t, carry);
+                    else
+                        focus_mask_count32(cnt, av[c & 1], bv[c & 1], t, carry);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else {
+                uint32_t av[Cfg::WX], bv[Cfg::WY];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                    for (int i = 0; i < Cfg::WX; ++i) av[i] = sb[(wx * Cfg::WX + i) * Cfg::ZS + 64 * c];
+#pragma unroll
+                    for (int j = 0; j < Cfg::WY; ++j) bv[j] = sb[(Cfg::TX + wy * Cfg::WY + j) * Cfg::ZS + 64 * c];
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (decltype(first_tag)::value && c == 0)
+                        focus_mask_count32_first(cnt, av, bv, t, carry);
+                    else
+                        focus_mask_count32(cnt, av, bv, t, carry);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         };
 
@@ -1002,12 +1022,12 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
 }
 
 // The whole-matrix form of pass1z_tile_g (square mode).
-template <int GX, int GY, int NC>
+template <int GX, int GY, int NC, bool AHEAD = true>
 __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float *__restrict__ D, int64_t n,
                                             int64_t ldd, int32_t *__restrict__ U, int64_t ldu,
                                             float *__restrict__ W, int64_t ldw, int64_t X0, int64_t Y0,
                                             int64_t zbeg, int64_t zend, bool atomic_mode, bool vec_ok) {
-    pass1z_tile_g<GX, GY, NC, false>(tid, smw, P1Rows{D, ldd, 0, n, D, ldd, 0, n}, n, U, ldu, W, ldw, X0, Y0, zbeg,
+    pass1z_tile_g<GX, GY, NC, false, AHEAD>(tid, smw, P1Rows{D, ldd, 0, n, D, ldd, 0, n}, n, U, ldu, W, ldw, X0, Y0, zbeg,
                                      zend, atomic_mode, vec_ok);
 }
 
@@ -1030,11 +1050,16 @@ __device__ __forceinline__ void pass1z_tile(int tid, uint32_t *smw, const float 
 #ifndef PALD_P1Z_NC
 #define PALD_P1Z_NC 2
 #endif
-// 6 waves per SIMD (3 workgroups per CU) is what the tile is built for; the
-// bound keeps a code change from quietly taking the kernel past 80 VGPRs and
-// down to 2 workgroups per CU (83 VGPRs: 162 instead of 132 ms at n = 16384)
+// 8 waves per SIMD (4 workgroups per CU, 32 KB of LDS each) with the
+// component reads not run ahead (64 VGPRs): 123 ms at n = 16384, against 130
+// ms at 6 waves with them run ahead (76 VGPRs; at 6 waves without them, 132
+// ms).  The bound keeps a code change from quietly taking the kernel past 64
+// VGPRs and down to 3 workgroups per CU.
 #ifndef PALD_P1Z_MIN_WAVES
-#define PALD_P1Z_MIN_WAVES 6
+#define PALD_P1Z_MIN_WAVES 8
+#endif
+#ifndef PALD_P1Z_AHEAD
+#define PALD_P1Z_AHEAD 0
 #endif
 using P1zMain = P1zCfg<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>;
 constexpr int P1Z_TX = P1zMain::TX, P1Z_TY = P1zMain::TY, P1Z_NT = P1zMain::NT, P1Z_ZS = P1zMain::ZS;
@@ -1054,7 +1079,7 @@ __global__ __launch_bounds__(P1Z_NT, PALD_P1Z_MIN_WAVES) void pass1z_focus_kerne
     if (X0 >= n) return;  // a later part of a square tile at the edge: no pairs
     const int64_t zbeg = (int64_t)blockIdx.y * z_per_chunk;
     const int64_t zend = min(n, zbeg + (int64_t)z_per_chunk);
-    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
+    pass1z_tile<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC, (bool)PALD_P1Z_AHEAD>((int)threadIdx.x, smw, D, n, ldd, U, ldu, W, ldw, X0, Y0, zbeg, zend,
                                    atomic_mode != 0, vec_ok != 0);
 }
 

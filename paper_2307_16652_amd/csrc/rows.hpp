@@ -24,8 +24,13 @@ namespace pald {
 // symmetric mirror; tile k of the launch piece starting at tile0 covers x
 // tile (tile0 + k) / ytiles and y tile (tile0 + k) % ytiles, so consecutive
 // workgroups share their x rows.
+// (the single-matrix tile's occupancy and component reads: 8 waves per SIMD,
+// no reads run ahead)
 #ifndef PALD_P1_ROWS_MIN_WAVES
-#define PALD_P1_ROWS_MIN_WAVES 6
+#define PALD_P1_ROWS_MIN_WAVES PALD_P1Z_MIN_WAVES
+#endif
+#ifndef PALD_P1_ROWS_AHEAD
+#define PALD_P1_ROWS_AHEAD PALD_P1Z_AHEAD
 #endif
 __global__ __launch_bounds__(P1Z_NT, PALD_P1_ROWS_MIN_WAVES) void pass1_rows_kernel(const P1Rows g, int64_t n,
                                                                                 int32_t *__restrict__ U, int64_t ldu,
@@ -35,7 +40,7 @@ __global__ __launch_bounds__(P1Z_NT, PALD_P1_ROWS_MIN_WAVES) void pass1_rows_ker
     const int64_t ytiles = (g.yhi - g.ylo + P1Z_TY - 1) / P1Z_TY;
     const int64_t k = tile0 + (int64_t)blockIdx.x;
     const int64_t X0 = g.xlo + (k / ytiles) * P1Z_TX, Y0 = g.ylo + (k % ytiles) * P1Z_TY;
-    pass1z_tile_g<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC, true>((int)threadIdx.x, smw, g, n, U, ldu, Wt, ldwt, X0, Y0,
+    pass1z_tile_g<PALD_P1Z_GX, PALD_P1Z_GY, PALD_P1Z_NC, true, (bool)PALD_P1_ROWS_AHEAD>((int)threadIdx.x, smw, g, n, U, ldu, Wt, ldwt, X0, Y0,
                                                                0, n, false, vec_ok != 0);
 }
 

@@ -124,18 +124,22 @@ __global__ void batch_reset_kernel(uint32_t *__restrict__ ctr, int64_t nctr, uin
 // the list, as the single-matrix kernels do for L2 reuse, would hand one XCD
 // all the tiles of the largest matrices: 121.6 instead of 117.4 ms per
 // 2000-matrix batch.)
-// The tile is 8 x 16 pairs of 4 waves (256 threads, compiled for 6 waves
-// per SIMD: 6 workgroups per CU), so that a CU holds more tiles whose
-// start-up overlaps the others' counting (121.7 ms per 2000-matrix batch
-// against 122.4 with the single-matrix 16 x 16 tile of 8 waves).
+// The tile is the single-matrix one, 16 x 16 pairs of 8 waves, compiled like
+// it for 8 waves per SIMD (64 VGPRs, 4 workgroups of 32 KB of LDS per CU)
+// with the component reads not run ahead: 95.0 ms per 2000-matrix batch,
+// against 96.5 with an 8 x 16 tile of 4 waves at 6 waves per SIMD (its 24 KB
+// of LDS allow no more than 6 workgroups per CU).
 #ifndef PALD_BATCH_P1Z_GX
-#define PALD_BATCH_P1Z_GX 2
+#define PALD_BATCH_P1Z_GX 4
 #endif
 #ifndef PALD_BATCH_P1Z_GY
 #define PALD_BATCH_P1Z_GY 2
 #endif
 #ifndef PALD_BATCH_P1Z_MIN_WAVES
-#define PALD_BATCH_P1Z_MIN_WAVES 6
+#define PALD_BATCH_P1Z_MIN_WAVES 8
+#endif
+#ifndef PALD_BATCH_P1Z_AHEAD
+#define PALD_BATCH_P1Z_AHEAD 0
 #endif
 using BatchFocusCfg = P1zCfg<PALD_BATCH_P1Z_GX, PALD_BATCH_P1Z_GY, PALD_P1Z_NC>;
 __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const int4 t,
@@ -148,7 +152,7 @@ __device__ __forceinline__ void batched_focus_one(int tid, uint32_t *smw, const 
     const bool vec_d = d_aligned && mats[mi].vec_d;
     if (stamps && tid == 0)
         atomicMin((unsigned long long *)&stamps[2 * mi], (unsigned long long)wall_clock64());
-    pass1z_tile<PALD_BATCH_P1Z_GX, PALD_BATCH_P1Z_GY, PALD_P1Z_NC>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n,
+    pass1z_tile<PALD_BATCH_P1Z_GX, PALD_BATCH_P1Z_GY, PALD_P1Z_NC, (bool)PALD_BATCH_P1Z_AHEAD>(tid, smw, D + moff, n, n, U ? U + moff : nullptr, n,
                                                                  Wr + mwoff, ldw, t.y, t.z, 0, n, false, vec_d);
 }
 

@@ -319,3 +319,22 @@ def test_config_batch_2000_sampled():
     log(f"[batched] max rel err {err:.3e} over the 100 oracle matrices")
     for i in range(len(mats)):
         check_invariants(Us[i], Cs[i], f"batch2000 matrix {i}")
+
+
+def test_tuner_timing_helpers():
+    """The autotuner's two timing helpers run on the GPU: one batched candidate
+    (the 2000-matrix batch, results checked against the first candidate's) and
+    one single-matrix evaluation."""
+    import torch
+
+    from paper_2307_16652_amd import pald, tune
+
+    dev = torch.device("cuda:0")
+    batch = tune.Batch(dev)
+    cfg = tune.config_of(pald, [1] * len(tune.BUCKETS), 0, 0, [64] * len(tune.BUCKETS), True)
+    ms = batch.time(cfg, 1)
+    assert 0.0 < ms < 10_000.0
+    assert batch.time(cfg, 1) > 0.0  # the second call compares its results with the first's
+    n = 256
+    Dg = torch.from_numpy(synth.mixture8d(n=n, seed=7)).to(dev)
+    assert tune._time_cohesion(pald, torch, Dg, n, 1, variant="pairwise") > 0.0

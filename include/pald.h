@@ -162,7 +162,9 @@ pald_status pald_cohesion(const float *D, int64_t n, int64_t ldd,
  * device memory: code under stream capture, tight serving loops, harnesses
  * that forbid hipMalloc.  It calls no hipMalloc, hipFree or other allocating
  * routine; its workspace is a device array of PALD_NOALLOC_SCRATCH_BYTES
- * inside the library, one per GPU.
+ * inside the library, one per GPU.  (Its pass-1 kernel keeps a few values
+ * per lane in the private segment, 16 bytes, which the HIP runtime provides
+ * at launch as for any kernel.)
  *   D, U, C, stream, opt  as for pald_cohesion (the caller still owns and
  *                         passes the inputs and outputs)
  * The plan is the one pald_cohesion uses with `opt`, except that an automatic

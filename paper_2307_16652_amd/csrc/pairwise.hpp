@@ -750,7 +750,9 @@ __device__ __forceinline__ void pass1z_tile_g(int tid, uint32_t *smw, const P1Ro
                                               bool atomic_mode, bool vec_ok) {
     using Cfg = P1zCfg<GX, GY, NC>;
     constexpr int RPW = Cfg::ROWS_PER_WAVE;
-    const int lane = tid & 63;
+    // (the lane index from the lane counter rather than from tid, so that no
+    // register has to hold tid across the tile)
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wx = wave % GX, wy = wave / GX;
     const int64_t xw = X0 + wx * Cfg::WX, yw = Y0 + wy * Cfg::WY;
